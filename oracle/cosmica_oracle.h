@@ -1,0 +1,140 @@
+/*
+ * cosmica_oracle.h -- plain FP64 CPU oracle for the backward-in-time SDE
+ * integration of heliospheric cosmic-ray quasi-particles (COSMICA, arXiv
+ * 2502.06319).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the correctness reference that
+ * the GPU path is compared against.  Only the test suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it.  It shares no source,
+ * header, table or helper with the HIP library; both sides only consume the
+ * same seeded physical inputs.
+ *
+ * What it computes (paper sections / equations):
+ *   - the momentum form of the Parker transport equation, Eq.(5), written in
+ *     the backward Kolmogorov form of Eq.(2) (Sec. III), integrated as the
+ *     Ito SDE of Eq.(3) with the Euler-Maruyama scheme (Sec. III);
+ *   - the adiabatic term A_P = (2/3)(V/r)P of Eq.(6) with no loss term (L=0);
+ *   - the exit-rigidity histogram and the LIS-weighted modulated flux of
+ *     Eq.(4) (Sec. III, Sec. IV.A);
+ *   - random numbers from the Philox4x32-10 counter-based generator cited in
+ *     Sec. IV.A (Salmon et al., SC'11), written from that paper.
+ * Every coefficient the paper leaves to its external references is a stated
+ * reading (the design notes list them); the formulas are the ones spelled out
+ * next to each function below.
+ *
+ * Units inside the oracle: AU, s, GV, GeV.  Inputs arrive in the physical units
+ * of the workload description (cm^2/s, km/s, degrees, nT, rad/s, GeV).
+ */
+#ifndef COSMICA_ORACLE_H
+#define COSMICA_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAX_REGIONS 15
+#define ORC_NHIST 129 /* 128 log-ratio bins over [0,3) decades + overflow */
+
+typedef struct {
+    int32_t model;            /* 0: radial 1D model, 1: full 3D model */
+    int32_t n_regions;        /* 1..15 equal-width radial shells */
+    double r_boundary_au;     /* absorbing spherical boundary */
+    double r0_au, theta0_rad, phi0_rad; /* injection point */
+    double kappa0_cm2_s[ORC_MAX_REGIONS];
+    double v_slow_km_s[ORC_MAX_REGIONS];
+    double tilt_deg[ORC_MAX_REGIONS];
+    double v_fast_km_s;       /* wind outside the slow band (3D) */
+    double b0_nT;             /* |B| at 1 AU on the ecliptic for v_ref */
+    double v_ref_km_s;        /* wind speed that fixes the B normalisation */
+    double omega_rad_s;       /* solar rotation rate */
+    double kperp_over_kpar;   /* kappa_perp / kappa_par (3D) */
+    int32_t polarity;         /* A = +1 or -1 */
+    int32_t drift;            /* 1: gradient-curvature drift on */
+    int32_t hcs;              /* 1: wavy current sheet (field reversal + sheet drift) */
+    int32_t flip_z2;          /* test hook: use -z2 for the theta noise (mirror test) */
+    double dt_max_s;
+    double dt_diff_frac;      /* dt <= frac * r^2 / kappa */
+    double dt_adv_frac;       /* 3D: dt <= frac * r / |A_det|; <= 0 disables */
+    double mass_gev;          /* rest mass of the nucleus / particle */
+    int32_t charge;           /* Z, signed */
+    int32_t pad0;
+    double lis_norm, lis_index; /* J_LIS(P) = norm * P^-index */
+    uint64_t seed;            /* Philox key */
+    uint32_t job_tag;         /* fourth Philox counter word */
+    uint32_t step_cap;        /* particles still inside after this many steps are flagged */
+} orc_params;
+
+enum { ORC_FLAG_CAPPED = 1, ORC_FLAG_NAN = 2 };
+
+typedef struct {
+    double P;      /* exit rigidity [GV] */
+    double t;      /* backward time to exit [s] */
+    double r, theta, phi;
+    uint32_t n;    /* number of Euler-Maruyama steps */
+    uint32_t flags;
+} orc_exit;
+
+/* Local SDE coefficients of the 3D model at one point, for unit-level pins. */
+typedef struct {
+    int32_t region;
+    double V;                 /* local wind speed [AU/s] */
+    double kpar, kperp;       /* [AU^2/s] */
+    double Krr, Kpp, Krp, Ktt;  /* physical components of the symmetric tensor */
+    double dKrr_dr;           /* d/dr K_rr */
+    double dKrp_term;         /* (1/r) d/dr (r K_rphi) */
+    double Brr, Bpr, Bpp, Btt;  /* B with B B^T = 2K (lower triangular in (r,phi)) */
+    double Bmag_nT;           /* |B| */
+    double Gamma;             /* Parker spiral: tan of the winding angle */
+    double G;                 /* kappa_A / sqrt(1+Gamma^2) [AU^2/s] */
+    double Hw;                /* field-polarity factor across the current sheet */
+    double sign_qA;           /* sign(Z) * A */
+    double vd[3];             /* total drift velocity, physical (r, theta, phi) [AU/s] */
+    double A[3];              /* drift of the SDE: dr, dtheta, dphi per unit time */
+    double AP;                /* dP/ds [GV/s] */
+    double dt;                /* time step [s] */
+} orc_coeffs;
+
+/* Philox4x32-10 of (key = seed, counter ctr[4]) -> out[4]. */
+void orc_philox4x32_10(uint64_t seed, const uint32_t ctr[4], uint32_t out[4]);
+
+/* Four standard normals from one Philox block (two Box-Muller pairs). */
+void orc_normals(uint64_t seed, const uint32_t ctr[4], double z[4]);
+
+/* Local 3D coefficients at (P, r, theta, phi). */
+void orc_coeffs_3d(const orc_params* p, double P, double r, double theta, double phi,
+                   orc_coeffs* out);
+
+/* Propagate particles first..first+count-1 of one rigidity bin to the boundary.
+ * out[i] receives particle first+i.  n_threads <= 0 uses OpenMP's default.
+ * Returns 0, or -1 on invalid parameters. */
+int orc_propagate(const orc_params* p, uint32_t bin_index, double P0_gv,
+                  uint32_t first, uint32_t count, orc_exit* out, int n_threads);
+
+/* Propagate one particle, stopping early after max_steps (checkpoint test):
+ * state in/out is (r, theta, phi, P, t, n); returns 1 if it exited. */
+int orc_advance(const orc_params* p, uint32_t bin_index, uint32_t particle,
+                double state[5], uint32_t* n, uint32_t max_steps);
+
+/* Per-bin results of Eq.(4) with f = J/P^2 (Sec. VI, Version 6). */
+typedef struct {
+    uint32_t hist[ORC_NHIST];
+    double flux;        /* J_mod(P0) */
+    double flux_se;     /* Monte Carlo standard error of J_mod */
+    double mean_exit_time_s;
+    uint64_t steps;     /* total EM steps of the bin */
+    uint32_t n_capped;
+    uint32_t n_nan;
+    uint32_t n_used;
+} orc_bin_result;
+
+void orc_reduce_bin(const orc_params* p, double P0_gv, const orc_exit* rec, uint32_t n,
+                    orc_bin_result* res);
+
+/* J_LIS of the parameters at rigidity P [GV]. */
+double orc_lis(const orc_params* p, double P_gv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

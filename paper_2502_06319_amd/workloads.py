@@ -1,0 +1,200 @@
+"""Seeded synthetic inputs for the quasi-particle SDE engine.
+
+This module only *draws and lists physical inputs* (heliosphere parameters in
+cm^2/s, km/s, degrees, nT; species masses in GeV; rigidity bins in GV;
+particle counts; RNG identities).  It holds none of the method's arithmetic:
+unit conversions, coefficients and the integration live separately in the
+GPU library and in the CPU oracle, and both consume these dictionaries.
+
+The paper's own workloads (HelMod period parameters, Galprop LIS tables,
+AMS-02 data; Sec. II.B, Sec. VII) are not available, so synthetic stand-ins
+with the same structure are used: 15 radial shells of the inner heliosphere
+(Sec. II.B), several isotopes, log-spaced rigidity checkpoints (Sec. VII), a
+power-law LIS.
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+# Rest masses [GeV] (CODATA 2018) and signed charges.
+SPECIES = {
+    "p": {"name": "p", "mass_gev": 0.93827208816, "charge": 1, "mass_number": 1},
+    "He4": {"name": "He4", "mass_gev": 3.7273794066, "charge": 2, "mass_number": 4},
+    "He3": {"name": "He3", "mass_gev": 2.80839160743, "charge": 2, "mass_number": 3},
+    "e-": {"name": "e-", "mass_gev": 0.51099895e-3, "charge": -1, "mass_number": 0},
+}
+SPECIES_ORDER = ("p", "He4", "He3", "e-")
+
+LIS_NORM = 1.9e4
+LIS_INDEX = 2.78
+STEP_CAP = 10_000_000
+
+
+def log_bins(p_min: float, p_max: float, n: int) -> list[float]:
+    """n rigidity checkpoints from p_min to p_max, log-spaced, endpoints included."""
+    if n == 1:
+        return [float(p_min)]
+    return [float(p_min * (p_max / p_min) ** (i / (n - 1))) for i in range(n)]
+
+
+def species(name: str) -> dict:
+    s = dict(SPECIES[name])
+    s["lis_norm"] = LIS_NORM
+    s["lis_index"] = LIS_INDEX
+    return s
+
+
+def helio_1d(kappa0=1.5e22, v=400.0, r_boundary=100.0, dt_max=5e4) -> dict:
+    """Spherically symmetric heliosphere with one shell (radial model)."""
+    return {
+        "model": 0,
+        "n_regions": 1,
+        "kappa0_cm2_s": [float(kappa0)],
+        "v_slow_km_s": [float(v)],
+        "tilt_deg": [0.0],
+        "v_fast_km_s": float(v),
+        "r_boundary_au": float(r_boundary),
+        "r0_au": 1.0,
+        "theta0_rad": math.pi / 2,
+        "phi0_rad": 0.0,
+        "b0_nT": 5.0,
+        "v_ref_km_s": 400.0,
+        "omega_rad_s": 2.66e-6,
+        "kperp_over_kpar": 1.0,
+        "polarity": 1,
+        "drift": 0,
+        "hcs": 0,
+        "dt_max_s": float(dt_max),
+        "dt_diff_frac": 0.02,
+        "dt_adv_frac": 0.0,
+    }
+
+
+def helio_3d(kappa0, v_slow, tilt_deg, polarity=1, r_boundary=120.0, drift=1, hcs=1,
+             kperp_over_kpar=0.02, v_fast=760.0, dt_max=5e4, dt_adv_frac=0.1) -> dict:
+    """Full 3D heliosphere: equal-width shells, each with (kappa0, Vslow, tilt)."""
+    kappa0 = [float(x) for x in np.atleast_1d(kappa0)]
+    v_slow = [float(x) for x in np.atleast_1d(v_slow)]
+    tilt_deg = [float(x) for x in np.atleast_1d(tilt_deg)]
+    n = len(kappa0)
+    assert len(v_slow) == n and len(tilt_deg) == n and 1 <= n <= 15
+    return {
+        "model": 1,
+        "n_regions": n,
+        "kappa0_cm2_s": kappa0,
+        "v_slow_km_s": v_slow,
+        "tilt_deg": tilt_deg,
+        "v_fast_km_s": float(v_fast),
+        "r_boundary_au": float(r_boundary),
+        "r0_au": 1.0,
+        "theta0_rad": math.pi / 2,
+        "phi0_rad": 0.0,
+        "b0_nT": 5.0,
+        "v_ref_km_s": 400.0,
+        "omega_rad_s": 2.66e-6,
+        "kperp_over_kpar": float(kperp_over_kpar),
+        "polarity": int(polarity),
+        "drift": int(drift),
+        "hcs": int(hcs),
+        "dt_max_s": float(dt_max),
+        "dt_diff_frac": 0.02,
+        "dt_adv_frac": float(dt_adv_frac),
+    }
+
+
+def draw_helio_3d(rng: np.random.Generator, polarity=None) -> dict:
+    """One synthetic parameter set: 15 shells with kappa0 ~ U[0.5,3]e22 cm^2/s,
+    Vslow ~ U[350,750] km/s, tilt ~ U[5,75] deg; polarity +-1 with equal odds
+    unless given."""
+    k0 = rng.uniform(0.5e22, 3.0e22, 15)
+    vs = rng.uniform(350.0, 750.0, 15)
+    tilt = rng.uniform(5.0, 75.0, 15)
+    pol = int(polarity) if polarity is not None else (1 if rng.uniform() < 0.5 else -1)
+    return helio_3d(k0, vs, tilt, polarity=pol)
+
+
+def make_job(helio: dict, spec: dict, rigidities, counts, seed=42, job_tag=0) -> dict:
+    rig = [float(x) for x in rigidities]
+    cnt = [int(x) for x in np.broadcast_to(np.asarray(counts), (len(rig),))]
+    return {
+        "helio": copy.deepcopy(helio),
+        "species": dict(spec),
+        "rigidity_gv": rig,
+        "particles_per_bin": cnt,
+        "seed": int(seed),
+        "job_tag": int(job_tag),
+        "step_cap": STEP_CAP,
+    }
+
+
+# --------------------------------------------------------------------------
+# The five workloads (config 1..5).
+# --------------------------------------------------------------------------
+
+def c1_job(particles_per_bin=1024, seed=42) -> dict:
+    """Radial model, protons, R=100 AU, V=400 km/s, kappa0=1.5e22 cm^2/s, no drift;
+    8 log-spaced rigidities 0.5-20 GV; 1,024 particles per bin; Philox seed 42."""
+    return make_job(helio_1d(), species("p"), log_bins(0.5, 20.0, 8), particles_per_bin,
+                    seed=seed, job_tag=0)
+
+
+def c2_helio(seed=42) -> dict:
+    rng = np.random.default_rng(seed)
+    return draw_helio_3d(rng, polarity=1)
+
+
+def c2_job(particles_per_bin=5000, seed=42, n_bins=20) -> dict:
+    """Full 3D model, protons, A>0, one 15-shell parameter set drawn with seed 42;
+    20 log-spaced rigidities 0.1-100 GV; 5,000 particles per bin."""
+    return make_job(c2_helio(seed), species("p"), log_bins(0.1, 100.0, n_bins),
+                    particles_per_bin, seed=seed, job_tag=0)
+
+
+def c4_jobs(seed=42, n_sets=64, species_names=SPECIES_ORDER, n_bins=30,
+            n_min=500, n_max=20000, count_scale=1.0) -> list[dict]:
+    """Batched workload: n_sets parameter sets x species x n_bins rigidities
+    0.1-100 GV, particles per bin log-uniform in [n_min, n_max]."""
+    rng = np.random.default_rng(seed)
+    sets = [draw_helio_3d(rng) for _ in range(n_sets)]
+    bins = log_bins(0.1, 100.0, n_bins)
+    jobs = []
+    tag = 0
+    for h in sets:
+        for sp in species_names:
+            n = np.rint(np.exp(rng.uniform(math.log(n_min), math.log(n_max), n_bins)))
+            n = np.maximum(1, np.rint(n * count_scale)).astype(int)
+            jobs.append(make_job(h, species(sp), bins, n, seed=seed, job_tag=tag))
+            tag += 1
+    return jobs
+
+
+def c5_requests(seed=42, rate_hz=5.0, duration_s=600.0, n_min=1000, n_max=100000,
+                bins_min=10, bins_max=50, count_scale=1.0, max_requests=None) -> list[dict]:
+    """Poisson stream of spectrum requests.  Each carries one random parameter set
+    and species, U{bins_min..bins_max} rigidity bins over 0.1-100 GV and
+    log-uniform [n_min, n_max] particles per bin; each has its own seed."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    reqs = []
+    i = 0
+    while True:
+        t += rng.exponential(1.0 / rate_hz)
+        if t > duration_s or (max_requests is not None and i >= max_requests):
+            break
+        h = draw_helio_3d(rng)
+        sp = SPECIES_ORDER[int(rng.integers(0, len(SPECIES_ORDER)))]
+        nb = int(rng.integers(bins_min, bins_max + 1))
+        n = np.rint(np.exp(rng.uniform(math.log(n_min), math.log(n_max), nb)))
+        n = np.maximum(1, np.rint(n * count_scale)).astype(int)
+        req_seed = int(rng.integers(1, 2**63 - 1))
+        job = make_job(h, species(sp), log_bins(0.1, 100.0, nb), n, seed=req_seed, job_tag=i)
+        reqs.append({"arrival_s": t, "job": job})
+        i += 1
+    return reqs
+
+
+def total_particles(jobs) -> int:
+    return int(sum(sum(j["particles_per_bin"]) for j in jobs))
