@@ -1,0 +1,270 @@
+"""Benchmark: quasi-particle SDE steps/s of the batched mixed-precision path.
+
+One timed "step" is one full pass of the hot path over the batched workload
+(64 heliosphere parameter sets x 4 species x 30 rigidity bins 0.1-100 GV,
+particles per bin log-uniform in [500, 20000], ~4.0e7 quasi-particles): every
+particle is integrated backward in time to the heliospheric boundary by the
+persistent propagation kernel, then every bin is histogrammed and LIS-weighted
+by the reduction kernel.  Inputs are resident in device memory (a plan) before
+the timed region starts.
+
+The JSON line also carries: spectra/hour, the plain FP64 GPU path on the same
+workload mix, serving p50/p99 latency under a Poisson request stream, the
+roofline of the propagation kernel (ALU-bound; algorithmic VALU lane-operations
+per step) and the FP64 CPU oracle timed on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2502_06319_amd import cosmica as C  # noqa: E402
+from paper_2502_06319_amd import workloads as W  # noqa: E402
+
+TUNE_CACHE = os.path.join(ROOT, "paper_2502_06319_amd", "tuned_launch.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "propagate_batched_mixed_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2502_06319_amd", "csrc", "kernels.hip")
+
+# Algorithmic VALU lane-operations of one Euler-Maruyama step, counted from the
+# formulas the kernels evaluate (each add, multiply, fused multiply-add,
+# compare/select, conversion, integer op and hardware transcendental = 1).
+OPS_PER_STEP = {
+    "3d": {"philox4x32_10": 80, "uniforms": 16, "box_muller": 12, "region_geometry": 13,
+           "beta_kappa": 9, "spiral_weights": 10, "tensor_and_divergence": 10,
+           "drift_prelude": 9, "current_sheet": 44, "gradient_curvature": 20,
+           "drift_vector": 14, "time_step": 15, "tensor_sqrt": 12, "em_update": 31},
+    "1d": {"philox4x32_10": 80, "uniforms": 8, "box_muller": 5, "region": 3,
+           "beta_kappa": 7, "coefficients": 12, "time_step": 5, "em_update": 13},
+}
+# Peak VALU lane-operation rates: 256 CUs x 2.4 GHz x 128 FP32 lanes/clk
+# (157.3 TFLOP/s / 2 flops per FMA) and x 64 FP64 lanes/clk (78.6 TFLOP/s / 2).
+PEAK_TOPS = {"mixed": 78.6, "fp64": 39.3}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def tuned_engine_launch(eng: C.Engine) -> dict:
+    """Launch shapes picked by the tuner (cached per device architecture)."""
+    out = {}
+    for prec in ("mixed", "fp64"):
+        out[prec] = eng.tune(C.MODEL_3D, prec, TUNE_CACHE)
+    return out
+
+
+def kernel_digest() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch of the propagation kernel from the rocprofv3 counter
+    runs, if they were taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_digest") != kernel_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_plan(eng, plan, steps, warmup, sync):
+    for _ in range(warmup):
+        plan.execute()
+        eng.timings()
+    prop, red, nsteps = [], [], []
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.execute()
+        t = eng.timings()  # waits on the stream; HIP-event durations of this pass
+        prop.append(t["propagate_ms"])
+        red.append(t["reduce_ms"])
+        nsteps.append(t["steps"])
+    sync()
+    wall = time.perf_counter() - t0
+    return wall, prop, red, nsteps, t
+
+
+def serve(eng, seconds, rate, precision, seed=42):
+    """Replay a Poisson stream of spectrum requests; latency = arrival -> result."""
+    reqs = W.c5_requests(seed=seed, rate_hz=rate, duration_s=seconds)
+    tickets = []
+    lat = []
+    done = threading.Event()
+    t0 = time.perf_counter()
+
+    def submitter():
+        for r in reqs:
+            dt = r["arrival_s"] - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append((r["arrival_s"], eng.submit(r["job"], precision)))
+        done.set()
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    steps = 0
+    finished = 0
+    pending = []
+    while not (done.is_set() and finished == len(tickets)):
+        while len(pending) < len(tickets):
+            pending.append(tickets[len(pending)])
+        for i, (arr, tk) in enumerate(pending):
+            if tk is None:
+                continue
+            ok, st = tk.poll()
+            if ok:
+                lat.append(time.perf_counter() - t0 - arr)
+                steps += int(tk.result()["steps"].sum())
+                pending[i] = (arr, None)
+                finished += 1
+        time.sleep(0.002)
+    th.join()
+    span = time.perf_counter() - t0
+    lat = np.array(lat)
+    return {
+        "requests": len(reqs), "rate_hz": rate, "seconds": round(span, 2),
+        "p50_latency_s": round(float(np.percentile(lat, 50)), 3) if len(lat) else None,
+        "p99_latency_s": round(float(np.percentile(lat, 99)), 3) if len(lat) else None,
+        "spectra_per_hour": round(len(lat) / span * 3600.0, 1),
+        "steps_per_s": float(steps / span),
+    }
+
+
+def cpu_baseline(seconds_target=12.0):
+    """The FP64 oracle on a bounded, seeded sample of the batched workload."""
+    from oracle import oracle as O
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    jobs = W.c4_jobs()
+    rng = np.random.default_rng(7)
+    picks = [(int(rng.integers(len(jobs))), int(rng.integers(30))) for _ in range(64)]
+    per = 96
+    steps = 0
+    t0 = time.perf_counter()
+    used = 0
+    for ji, b in picks:
+        r = O.run_job(jobs[ji], threads=threads, bins=[b], count=per)[0]
+        steps += int(r["steps"])
+        used += 1
+        if time.perf_counter() - t0 > seconds_target:
+            break
+    wall = time.perf_counter() - t0
+    return {"value": float(steps / wall), "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{used} seeded (job, bin) pairs of the batched workload x {per} particles, "
+                      f"{steps} steps in {wall:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--plain-scale", type=float, default=0.25,
+                    help="particle-count scale of the plain FP64 comparison pass")
+    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the quasi-particles are "
+              "independent and a multi-GPU run would shard whole bins; see the design notes.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch  # device synchronisation around the timed region
+
+    sync = torch.cuda.synchronize
+    eng = C.Engine(0)
+    launch = tuned_engine_launch(eng)
+    log("launch shapes:", launch)
+
+    jobs = W.c4_jobs()
+    n_particles = W.total_particles(jobs)
+    plan = eng.plan(jobs, "mixed")
+    log(f"batched workload: {len(jobs)} spectra, {n_particles} particles")
+    wall, prop, red, nsteps, last = time_plan(eng, plan, args.steps, args.warmup, sync)
+    steps_total = int(sum(nsteps))
+    value = steps_total / wall
+    ms_per_step = wall / args.steps * 1e3
+    spectra_per_hour = len(jobs) * args.steps / wall * 3600.0
+    prop_avg = float(np.mean(prop))
+    log(f"mixed: {value:.4e} steps/s, {ms_per_step:.1f} ms per pass, propagate {prop_avg:.1f} ms")
+    res = plan.read()
+    assert sum(int(r["n_nan"].sum()) for r in res) == 0
+    plan.destroy()
+
+    ops = sum(OPS_PER_STEP["3d"].values())
+    steps_per_launch = nsteps[-1]
+    achieved = ops * steps_per_launch / (prop_avg * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TOPS["mixed"],
+                "unit": "Tops/s", "frac": round(achieved / PEAK_TOPS["mixed"], 4),
+                "traffic": read_traffic(), "kernel": "k_propagate<float,3d>",
+                "ops_per_step": ops, "steps_per_launch": steps_per_launch,
+                "avg_launch_ms": round(prop_avg, 3)}
+
+    plain = None
+    if not args.no_plain:
+        pjobs = W.c4_jobs(count_scale=args.plain_scale)
+        pplan = eng.plan(pjobs, "fp64")
+        pw, pprop, _, pn, _ = time_plan(eng, pplan, 1, 0, sync)
+        pplan.destroy()
+        p_rate = pn[0] / (pprop[0] * 1e-3)
+        m_rate = steps_per_launch / (prop_avg * 1e-3)
+        plain = {"steps_per_s": float(pn[0] / pw), "propagate_steps_per_s": float(p_rate),
+                 "particle_scale": args.plain_scale,
+                 "mixed_over_plain": round(m_rate / p_rate, 3),
+                 "fp64_ops_frac": round(ops * p_rate / 1e12 / PEAK_TOPS["fp64"], 4)}
+        log("plain fp64:", plain)
+
+    serving = None
+    if not args.no_serve:
+        serving = serve(eng, args.serve_seconds, 5.0, "mixed")
+        log("serving:", serving)
+    eng.close()
+
+    cpu = None if args.no_cpu else cpu_baseline()
+    if cpu:
+        log("cpu baseline:", cpu)
+
+    line = {
+        "metric": "quasi-particle SDE steps/s + spectra/hour vs plain; p50/p99 spectrum latency",
+        "value": float(value), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "batched: 64 heliosphere sets x 4 species (p, He-4, He-3, e-) x "
+                               "30 rigidity bins 0.1-100 GV, log-uniform 500-20000 particles per "
+                               "bin, full 3D model (Parker spiral, drift, wavy current sheet), "
+                               "one persistent mixed FP32/FP64 launch",
+                   "particles": n_particles, "spectra": len(jobs), "seed": 42,
+                   "launch": launch["mixed"], "parallelism": "1 GPU"},
+        "spectra_per_hour": round(spectra_per_hour, 1),
+        "plain_fp64": plain, "serving": serving,
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

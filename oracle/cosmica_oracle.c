@@ -92,6 +92,16 @@ void orc_normals(uint64_t seed, const uint32_t ctr[4], double z[4])
     z[3] = rho2 * sin(2.0 * ORC_PI * u3);
 }
 
+void orc_rng_block(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t n,
+                   uint32_t* words, double* z)
+{
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t ctr[4] = {c0 + i, c1, c2, c3};
+        if (words) orc_philox4x32_10(seed, ctr, words + 4 * (size_t)i);
+        if (z) orc_normals(seed, ctr, z + 4 * (size_t)i);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Per-job constants in internal units.                                      */
 /* ------------------------------------------------------------------------ */

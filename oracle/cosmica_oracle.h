@@ -101,6 +101,11 @@ void orc_philox4x32_10(uint64_t seed, const uint32_t ctr[4], uint32_t out[4]);
 /* Four standard normals from one Philox block (two Box-Muller pairs). */
 void orc_normals(uint64_t seed, const uint32_t ctr[4], double z[4]);
 
+/* Loops of the two calls above over counters (c0 + i, c1, c2, c3), i < n:
+ * words[4i..4i+3] and z[4i..4i+3] (either may be NULL). */
+void orc_rng_block(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t n,
+                   uint32_t* words, double* z);
+
 /* Local 3D coefficients at (P, r, theta, phi). */
 void orc_coeffs_3d(const orc_params* p, double P, double r, double theta, double phi,
                    orc_coeffs* out);

@@ -109,6 +109,8 @@ def lib():
                                         ctypes.POINTER(ctypes.c_uint32)]
         L.orc_normals.argtypes = [ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32),
                                   ctypes.POINTER(ctypes.c_double)]
+        L.orc_rng_block.argtypes = [ctypes.c_uint64] + [ctypes.c_uint32] * 5 + [
+            ctypes.c_void_p, ctypes.c_void_p]
         L.orc_coeffs_3d.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, ctypes.POINTER(OrcCoeffs)]
         L.orc_propagate.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_uint32, ctypes.c_double,
@@ -180,6 +182,14 @@ def normals(seed: int, ctr) -> np.ndarray:
     return np.array(list(o))
 
 
+def rng_block(seed: int, c0: int, c1: int, c2: int, c3: int, n: int):
+    """Philox words (n, 4) and normals (n, 4) for counters (c0 + i, c1, c2, c3)."""
+    w = np.zeros((n, 4), dtype=np.uint32)
+    z = np.zeros((n, 4))
+    lib().orc_rng_block(seed & (2**64 - 1), c0, c1, c2, c3, n, w.ctypes.data, z.ctypes.data)
+    return w, z
+
+
 def coeffs_3d(p: OrcParams, P, r, theta, phi) -> dict:
     c = OrcCoeffs()
     lib().orc_coeffs_3d(ctypes.byref(p), P, r, theta, phi, ctypes.byref(c))
@@ -233,7 +243,9 @@ def run_job(job: dict, threads: int = 0, bins=None, count=None, first: int = 0,
     for b in sel:
         P0 = job["rigidity_gv"][b]
         n = job["particles_per_bin"][b] if count is None else count
-        rec = propagate(p, b, P0, n, first=first, threads=threads)
+        # the bin's random streams are those of bin index bin_offset + b
+        rec = propagate(p, int(job.get("bin_offset", 0)) + b, P0, n, first=first,
+                        threads=threads)
         res = reduce_bin(p, P0, rec)
         res["records"] = rec
         res["bin"] = b

@@ -1,0 +1,136 @@
+// engine.hpp -- device-side tables shared by the HIP kernels and the host
+// runtime of libcosmica (internal; not part of the C ABI).
+//
+// Units on the device: AU, s, GV.  The runtime converts the physical inputs of
+// cosmica.h once per job; kernels only read these tables.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cosmica {
+
+constexpr int kMaxRegions = 15;
+constexpr int kRegionStride = 16;  // region-table entries reserved per job
+constexpr int kNHist = 129;
+constexpr uint32_t kFlagCapped = 1u;
+constexpr uint32_t kFlagNaN = 2u;
+constexpr int kFlagShift = 24;  // exit word = n | flags << 24 (n < 2^24)
+
+// Per-job constants.  R is the bulk precision of the kernel (float for the
+// mixed kernel, double for the plain FP64 one); r, t, P and the geometry of the
+// boundary are always double.
+template <typename R>
+struct alignas(16) JobDev {
+    uint32_t seed_lo, seed_hi, job_tag, step_cap;
+    int32_t nreg, drift, hcs, pad0;
+    double rb;         // absorbing boundary [AU]
+    double inv_shell;  // n_regions / rb [1/AU]
+    double r0, th0, ph0, pad1;
+    R vf;          // fast wind [AU/s]
+    R omega;       // solar rotation [rad/s]
+    R kperp_frac;  // kappa_perp / kappa_par
+    R gcoef;       // kappa_A / sqrt(1+G^2) = gcoef * beta * P * r^2 / (1+G^2)
+    R br0;         // radial field at 1 AU [nT]
+    R abs_z, mass2;
+    R sqA;         // sign(Z) * polarity
+    R dt_max, diff_frac, adv_frac;
+    R rlcoef;      // Larmor radius [AU] = rlcoef * P[GV] / |B|[nT]
+};
+
+// One radial shell: kappa0 [AU^2/s], slow wind [AU/s], tilt [rad], tan(tilt),
+// omega / slow wind [rad/AU].
+template <typename R>
+struct alignas(16) RegionDev {
+    R k0, vs, alpha, tana, om_vs, pad0, pad1, pad2;
+};
+
+// One (job, rigidity bin) segment of the flat work index.
+struct alignas(16) SegmentDev {
+    double P0;
+    uint32_t job, bin, count, out_offset;
+    uint32_t pad0, pad1;
+};
+
+// A refill chunk: particles [first, first+count) of segment seg.
+struct alignas(16) ChunkDev {
+    uint32_t seg, first, count, pad0;
+};
+
+struct alignas(16) LisDev {
+    double norm, index;
+};
+
+// Suspended particle (serving slices): full state, bit-exact on resume.
+struct alignas(16) SuspendDev {
+    double r, P, t, th, ph;
+    uint32_t n, seg, pid, pad0;
+};
+
+template <typename R>
+struct PropArgs {
+    const JobDev<R>* jobs;
+    const RegionDev<R>* regions;  // jobs * kRegionStride
+    const SegmentDev* segs;
+    const ChunkDev* chunks;
+    uint32_t n_chunks;
+    uint32_t* head;               // chunk cursor, zeroed before launch
+    // exit records, indexed by segment out_offset + particle
+    double* exP;
+    double* exT;
+    uint32_t* exNF;
+    double* exR;   // optional (nullptr)
+    double* exTh;
+    double* exPh;
+    // serving slices: resume list in, suspend list out
+    const SuspendDev* resume;
+    uint32_t n_resume;
+    uint32_t* resume_head;        // cursor over the resume list, zeroed before launch
+    SuspendDev* suspend;
+    uint32_t* suspend_count;      // zeroed before launch
+    uint32_t step_budget;         // steps per lane per launch (0xffffffff: unlimited)
+    const uint32_t* job_cancel;   // optional per-job cancel flags
+    uint32_t* job_done;           // optional per-job count of finished particles
+    ChunkDev* leftover;           // chunk remainders a wave held when its slice ended
+    uint32_t* leftover_count;     // zeroed before launch
+};
+
+struct ReduceArgs {
+    const SegmentDev* segs;
+    const LisDev* lis;  // per job
+    const double* exP;
+    const double* exT;
+    const uint32_t* exNF;
+    uint32_t seg_base;  // first segment of this launch
+    uint32_t* hist;     // per segment: kNHist (may be null)
+    double* flux;
+    double* flux_se;
+    double* mean_t;
+    uint64_t* steps;
+    uint32_t* n_capped;
+    uint32_t* n_nan;
+    uint32_t out_base;  // output index of segment seg_base
+};
+
+// Launchers (kernels.hip).
+hipError_t launch_propagate_3d_mixed(const PropArgs<float>& a, int grid, int block, hipStream_t s);
+hipError_t launch_propagate_3d_fp64(const PropArgs<double>& a, int grid, int block, hipStream_t s);
+hipError_t launch_propagate_1d_mixed(const PropArgs<float>& a, int grid, int block, hipStream_t s);
+hipError_t launch_propagate_1d_fp64(const PropArgs<double>& a, int grid, int block, hipStream_t s);
+hipError_t occupancy_propagate(int model, int prec, int block, int* blocks_per_cu);
+hipError_t launch_reduce(const ReduceArgs& a, uint32_t n_segs, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint32_t n, hipStream_t s);
+
+// Diagnostics: raw Philox words and normals for counters (i, c1, c2, c3),
+// i = c0 .. c0+n-1; coefficients at given points.
+hipError_t launch_probe_rng(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
+                            uint32_t c3, uint32_t n, uint32_t* words, double* z64, float* z32,
+                            hipStream_t s);
+hipError_t launch_probe_coeffs_fp64(const JobDev<double>* job, const RegionDev<double>* reg,
+                                    const double* pts, uint32_t n, double* out, hipStream_t s);
+hipError_t launch_probe_coeffs_mixed(const JobDev<float>* job, const RegionDev<float>* reg,
+                                     const double* pts, uint32_t n, double* out, hipStream_t s);
+constexpr int kProbeOut = 16;
+
+}  // namespace cosmica

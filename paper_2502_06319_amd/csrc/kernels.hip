@@ -1,0 +1,763 @@
+// kernels.hip -- gfx950 kernels of libcosmica.
+//
+// propagate<R, 3D>: persistent Euler-Maruyama integrator of the backward SDE
+//   (arXiv 2502.06319, Eq.(3) applied to Eq.(5) with A_P of Eq.(6), Sec. III),
+//   one lane per quasi-particle (Sec. IV.A).  Lanes whose particle left the
+//   heliosphere are refilled from a flat work queue at the next step; each
+//   wave takes a whole refill chunk with one atomic and hands its particles to
+//   its idle lanes by ballot rank, so waves stay full until the queue drains.
+//   R = double is the plain FP64 path; R = float is the mixed path (bulk FP32
+//   with the hardware transcendentals, r / t / P accumulated in FP64).
+// reduce: one workgroup per rigidity bin; LDS-privatised exit histogram and
+//   fixed-order FP64 sums of the LIS weights (Eq.(4), J = f P^2, L = 0).
+//
+// No MFMA: the work is per-particle scalar arithmetic, bound by VALU issue
+// and the transcendental unit.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "engine.hpp"
+
+namespace cosmica {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr double kTwoPi = 6.283185307179586476925286766559005768;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11 -- the generator of Sec. IV.A).  Written
+// for gfx950: each 32x32->64 product is one v_mad_u64_u32.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t k0, uint32_t k1, uint32_t c0,
+                                               uint32_t c1, uint32_t c2, uint32_t c3)
+{
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)m1;
+        c3 = (uint32_t)m0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// ---------------------------------------------------------------------------
+// Precision traits.  float: gfx950 hardware ops (v_rcp/v_sqrt/v_rsq/v_log/
+// v_exp/v_sin/v_cos; sin/cos take revolutions).  double: IEEE FP64 library.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Mth;
+
+template <>
+struct Mth<float> {
+    // Floors that keep binary32 finite at the poles (where theta can round onto
+    // float(pi) and the hardware sine returns exactly 0) and at r -> 0.
+    static constexpr float kSinFloor = 1e-7f;
+    static constexpr float kRFloor = 1e-6f;
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float ln(float x)
+    {
+        return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
+    }
+    // sin(2 pi x), cos(2 pi x)
+    static __device__ __forceinline__ void sincos_rev(float x, float* s, float* c)
+    {
+        *s = __builtin_amdgcn_sinf(x);
+        *c = __builtin_amdgcn_cosf(x);
+    }
+    static __device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf(x); }
+    static __device__ __forceinline__ void sincos_rad(float x, float* s, float* c)
+    {
+        sincos_rev(x * 0.159154943091895336f, s, c);
+    }
+    static __device__ __forceinline__ float atan(float x) { return ::atanf(x); }
+    static __device__ __forceinline__ float tanh(float x)
+    {
+        // tanh|x| = (1 - e) / (1 + e), e = 2^(-2 |x| log2 e)
+        const float e = __builtin_amdgcn_exp2f(-2.88539008177792681f * fabsf(x));
+        return copysignf((1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e), x);
+    }
+    static __device__ __forceinline__ float fmod2pi(float x)
+    {
+        return ::fmodf(x, (float)kTwoPi);
+    }
+};
+
+template <>
+struct Mth<double> {
+    static constexpr double kSinFloor = 0.0;  // FP64 needs no floors
+    static constexpr double kRFloor = 0.0;
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
+    static __device__ __forceinline__ double ln(double x) { return ::log(x); }
+    static __device__ __forceinline__ void sincos_rev(double x, double* s, double* c)
+    {
+        ::sincospi(2.0 * x, s, c);
+    }
+    static __device__ __forceinline__ double cos_rev(double x) { return ::cospi(2.0 * x); }
+    static __device__ __forceinline__ void sincos_rad(double x, double* s, double* c)
+    {
+        ::sincos(x, s, c);
+    }
+    static __device__ __forceinline__ double atan(double x) { return ::atan(x); }
+    static __device__ __forceinline__ double tanh(double x) { return ::tanh(x); }
+    static __device__ __forceinline__ double fmod2pi(double x) { return ::fmod(x, kTwoPi); }
+};
+
+template <typename R>
+__device__ __forceinline__ R uniform_of(uint32_t x)
+{
+    // (floor(x / 2^9) + 1/2) * 2^-23: exact in binary32 and binary64
+    return ((R)(x >> 9) + (R)0.5) * (R)1.1920928955078125e-07;
+}
+
+// Box-Muller: z0, z1 from (u0, u1), z2 from (u2, u3).
+template <typename R, int NZ>
+__device__ __forceinline__ void normals(uint32_t k0, uint32_t k1, uint32_t n, uint32_t pid,
+                                        uint32_t bin, uint32_t tag, R* z)
+{
+    const uint4 x = philox4x32_10(k0, k1, n, pid, bin, tag);
+    const R rho0 = Mth<R>::sqrt((R)-2.0 * Mth<R>::ln(uniform_of<R>(x.x)));
+    if (NZ == 1) {
+        z[0] = rho0 * Mth<R>::cos_rev(uniform_of<R>(x.y));
+    } else {
+        R s1, c1;
+        Mth<R>::sincos_rev(uniform_of<R>(x.y), &s1, &c1);
+        const R rho2 = Mth<R>::sqrt((R)-2.0 * Mth<R>::ln(uniform_of<R>(x.z)));
+        z[0] = rho0 * c1;
+        z[1] = rho0 * s1;
+        z[2] = rho2 * Mth<R>::cos_rev(uniform_of<R>(x.w));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Particle state and one step.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct PState {
+    double r, P, t;
+    R th, ph;
+    uint32_t n;
+};
+
+// Local SDE coefficients of the 3D model (see cosmica.h for the model).
+template <typename R>
+struct Coef3 {
+    R Ar, At, Ap, AP;      // drift of the SDE (r, theta, phi per unit time), dP/ds
+    R Brr, Bpr, Bpp, Btt;  // B with B B^T = 2K
+    R dt;
+    R Hw, vdr, vdt, vdp, Krr, Krp, kpar;
+};
+
+template <typename R>
+__device__ __forceinline__ int region_of(const JobDev<R>& J, double r)
+{
+    const int k = (int)(r * J.inv_shell);
+    return k < J.nreg - 1 ? k : J.nreg - 1;
+}
+
+template <typename R, bool FULL>
+__device__ __forceinline__ void coeffs3d(const JobDev<R>& J, const RegionDev<R>& g, double rd,
+                                         double Pd, R th, R ph, Coef3<R>& c)
+{
+    using M = Mth<R>;
+    const R r0 = (R)rd;
+    const R r = r0 > M::kRFloor ? r0 : M::kRFloor;
+    const R P = (R)Pd;
+    R st, ct;
+    M::sincos_rad(th, &st, &ct);
+    st = st > M::kSinFloor ? st : M::kSinFloor;
+    const R invr = M::rcp(r);
+    const R invst = M::rcp(st);
+    const R cot = ct * invst;
+    // wind: slow inside |latitude| <= tilt of the shell, fast outside
+    const R lam = (R)(0.5 * kPi) - th;
+    const R V = (fabs(lam) <= g.alpha) ? g.vs : J.vf;
+    // diffusion tensor: k_par along b ~ (1, 0, -Gamma), k_perp across
+    const R pc = J.abs_z * P;
+    const R beta = pc * M::rsqrt(pc * pc + J.mass2);
+    const R kpar = g.k0 * beta * P;
+    const R kperp = J.kperp_frac * kpar;
+    const R dk = kpar - kperp;
+    const R w = J.omega * r * st;  // corotation speed; Gamma = w / V
+    const R V2 = V * V;
+    const R invD = M::rcp(V2 + w * w);
+    const R gq = V2 * invD;       // 1 / (1 + Gamma^2)
+    const R Gg = V * w * invD;    // Gamma / (1 + Gamma^2)
+    const R GGg = w * w * invD;   // Gamma^2 / (1 + Gamma^2)
+    const R Krr = kperp + dk * gq;
+    const R Krp = -dk * Gg;
+    // d/dr K_rr and (1/r) d/dr (r K_rphi), Gamma proportional to r
+    const R dKrr = (R)-2.0 * dk * GGg * gq * invr;
+    const R dKrp = (R)-2.0 * dk * Gg * gq * invr;
+
+    R vdr = 0, vdt = 0, vdp = 0, Hw = 1;
+    if (J.drift) {
+        const R invV = M::rcp(V);
+        const R Gam = w * invV;
+        const R Gam2 = Gam * Gam;
+        const R opg = (R)1.0 + Gam2;
+        const R gg = M::rcp(opg);
+        // kappa_A / sqrt(1 + Gamma^2), kappa_A = beta P / (3 |B|)
+        const R G = J.gcoef * beta * P * r * r * gg;
+        R vcr = 0, vct = 0, vcp = 0;
+        if (J.hcs) {
+            // wavy sheet: latitude atan(tan(alpha) sin(phi + Omega r / Vs)),
+            // polarity factor tanh((theta_cs - theta) / Delta), Delta = 2 r_L / r
+            R sc, cc;
+            M::sincos_rad(ph + g.om_vs * r, &sc, &cc);
+            const R tana = g.tana;
+            const R u = lam - M::atan(tana * sc);
+            const R Bmag = J.br0 * invr * invr * M::sqrt(opg);
+            const R invDelta = r * Bmag * M::rcp((R)2.0 * J.rlcoef * P);
+            Hw = M::tanh(u * invDelta);
+            const R Hp = (R)1.0 - Hw * Hw;
+            const R cs = -tana * cc * M::rcp((R)1.0 + tana * tana * sc * sc);
+            const R gr = cs * g.om_vs;          // d theta_cs / dr
+            const R gph = cs * invr * invst;    // (1/(r sin)) d theta_cs / dphi
+            // grad Hw x W, grad Hw = (Hp/Delta)(grad u - u grad ln Delta)
+            const R f = Hp * invDelta * G;
+            const R ug = u * gg * invr;
+            vcr = f * (Gam * invr - ug * Gam * Gam2 * cot);
+            vct = f * (gph + gr * Gam - ug * Gam);
+            vcp = f * (invr - ug * Gam2 * cot);
+        }
+        // gradient-curvature drift Hw curl(G (1, 0, -Gamma))
+        const R twoGg = (R)2.0 * G * gg;
+        vdr = J.sqA * (Hw * (-twoGg * J.omega * invV * ct) + vcr);
+        vdt = J.sqA * (Hw * (twoGg * Gam * ((R)2.0 + Gam2) * invr) + vct);
+        vdp = J.sqA * (Hw * (twoGg * Gam2 * cot * invr) + vcp);
+    }
+    c.Ar = (R)2.0 * Krr * invr + dKrr - V - vdr;
+    c.At = kperp * cot * invr * invr - vdt * invr;
+    c.Ap = (dKrp - vdp) * invr * invst;
+    c.AP = (R)(2.0 / 3.0) * V * P * invr;
+    // time step: min(dt_max, f_diff r^2 / k_par, f_adv r / |A_det|)
+    R dt = J.dt_max;
+    const R d1 = J.diff_frac * r * r * M::rcp(kpar);
+    dt = d1 < dt ? d1 : dt;
+    if (J.adv_frac > (R)0) {
+        const R at = r * c.At;
+        const R ap = r * st * c.Ap;
+        const R a2 = c.Ar * c.Ar + at * at + ap * ap;
+        if (a2 > (R)0) {
+            const R d2 = J.adv_frac * r * M::rsqrt(a2);
+            dt = d2 < dt ? d2 : dt;
+        }
+    }
+    c.dt = dt;
+    c.Brr = M::sqrt((R)2.0 * Krr);
+    c.Bpr = (R)2.0 * Krp * M::rcp(c.Brr);
+    c.Bpp = M::sqrt((R)2.0 * kpar * kperp * M::rcp(Krr));
+    c.Btt = M::sqrt((R)2.0 * kperp);
+    if (FULL) {
+        c.Hw = Hw;
+        c.vdr = vdr;
+        c.vdt = vdt;
+        c.vdp = vdp;
+        c.Krr = Krr;
+        c.Krp = Krp;
+        c.kpar = kpar;
+    }
+}
+
+// One EM step of the 3D model.  Returns nothing; the caller tests r >= rb.
+template <typename R>
+__device__ __forceinline__ void step3d(const JobDev<R>& J, const RegionDev<R>* __restrict__ reg,
+                                       PState<R>& s, uint32_t pid, uint32_t bin)
+{
+    using M = Mth<R>;
+    R z[3];
+    normals<R, 3>(J.seed_lo, J.seed_hi, s.n, pid, bin, J.job_tag, z);
+    const RegionDev<R> g = reg[region_of(J, s.r)];
+    Coef3<R> c;
+    coeffs3d<R, false>(J, g, s.r, s.P, s.th, s.ph, c);
+    const R dt = c.dt;
+    const R sdt = M::sqrt(dt);
+    const R r0 = (R)s.r;
+    const R r = r0 > M::kRFloor ? r0 : M::kRFloor;
+    const R invr = M::rcp(r);
+    R st, ct;
+    M::sincos_rad(s.th, &st, &ct);
+    st = st > M::kSinFloor ? st : M::kSinFloor;
+    double r1 = s.r + (double)(c.Ar * dt) + (double)(c.Brr * z[0] * sdt);
+    R th1 = s.th + c.At * dt + c.Btt * z[2] * sdt * invr;
+    R ph1 = s.ph + c.Ap * dt + (c.Bpr * z[0] + c.Bpp * z[1]) * sdt * (invr * M::rcp(st));
+    const double P1 = s.P + (double)(c.AP * dt);
+    if (r1 < 0.0) {
+        r1 = -r1;
+        th1 = (R)kPi - th1;
+        ph1 = ph1 + (R)kPi;
+    }
+    if (th1 < (R)0) {
+        th1 = -th1;
+        ph1 = ph1 + (R)kPi;
+    }
+    if (th1 > (R)kPi) {
+        th1 = M::fmod2pi(th1);
+        if (th1 > (R)kPi) {
+            th1 = (R)kTwoPi - th1;
+            ph1 = ph1 + (R)kPi;
+        }
+    }
+    if (ph1 < (R)0 || ph1 >= (R)kTwoPi) {
+        ph1 = M::fmod2pi(ph1);
+        if (ph1 < (R)0) ph1 = ph1 + (R)kTwoPi;
+    }
+    s.r = r1;
+    s.th = th1;
+    s.ph = ph1;
+    s.P = P1;
+    s.t = s.t + (double)dt;
+    s.n = s.n + 1u;
+}
+
+// One EM step of the radial model: dr = (2k/r - V) ds + sqrt(2k) dW.
+template <typename R>
+__device__ __forceinline__ void step1d(const JobDev<R>& J, const RegionDev<R>* __restrict__ reg,
+                                       PState<R>& s, uint32_t pid, uint32_t bin)
+{
+    using M = Mth<R>;
+    R z[1];
+    normals<R, 1>(J.seed_lo, J.seed_hi, s.n, pid, bin, J.job_tag, z);
+    const RegionDev<R> g = reg[region_of(J, s.r)];
+    const R r0 = (R)s.r;
+    const R r = r0 > M::kRFloor ? r0 : M::kRFloor;
+    const R P = (R)s.P;
+    const R invr = M::rcp(r);
+    const R pc = J.abs_z * P;
+    const R beta = pc * M::rsqrt(pc * pc + J.mass2);
+    const R kap = g.k0 * beta * P;
+    const R V = g.vs;
+    const R Ar = (R)2.0 * kap * invr - V;
+    const R Brr = M::sqrt((R)2.0 * kap);
+    const R AP = (R)(2.0 / 3.0) * V * P * invr;
+    R dt = J.dt_max;
+    const R d1 = J.diff_frac * r * r * M::rcp(kap);
+    dt = d1 < dt ? d1 : dt;
+    const R sdt = M::sqrt(dt);
+    double r1 = s.r + (double)(Ar * dt) + (double)(Brr * z[0] * sdt);
+    const double P1 = s.P + (double)(AP * dt);
+    if (r1 < 0.0) r1 = -r1;
+    s.r = r1;
+    s.P = P1;
+    s.t = s.t + (double)dt;
+    s.n = s.n + 1u;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent propagation kernel.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint32_t wave_uniform(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+template <typename R, bool M3D>
+__global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
+{
+    const uint32_t lane = __lane_id();
+    PState<R> s = {0.0, 0.0, 0.0, (R)0, (R)0, 0u};
+    uint32_t pid = 0, bin = 0, job = 0, out = 0, seg = 0;
+    bool active = false;
+    uint32_t budget = 0;  // steps this lane has taken in this launch
+
+    // wave-uniform refill cursors
+    uint32_t c_seg = 0, c_next = 0, c_end = 0;
+    bool resume_open = a.n_resume > 0;
+    bool queue_open = true;
+    bool launch_open = true;  // false once this wave used its step budget
+
+    for (;;) {
+        uint64_t need = __ballot(!active);
+        // 1) suspended particles of earlier slices come back first
+        while (need != 0 && resume_open && launch_open) {
+            uint32_t base = 0;
+            const uint32_t cnt = (uint32_t)__popcll(need);
+            if (lane == 0) base = atomicAdd(a.resume_head, cnt);
+            base = wave_uniform(base);
+            if (base >= a.n_resume) {
+                resume_open = false;
+                break;
+            }
+            const uint32_t rank = lane_rank(need);
+            if (!active && base + rank < a.n_resume) {
+                const SuspendDev q = a.resume[base + rank];
+                s.r = q.r;
+                s.P = q.P;
+                s.t = q.t;
+                s.th = (R)q.th;
+                s.ph = (R)q.ph;
+                s.n = q.n;
+                seg = q.seg;
+                pid = q.pid;
+                const SegmentDev sg = a.segs[seg];
+                job = sg.job;
+                bin = sg.bin;
+                out = sg.out_offset + pid;
+                active = true;
+            }
+            need = __ballot(!active);
+        }
+        // 2) new particles from the chunk queue
+        while (need != 0 && !resume_open && queue_open && launch_open) {
+            if (c_next == c_end) {
+                uint32_t c = 0;
+                if (lane == 0) c = atomicAdd(a.head, 1u);
+                c = wave_uniform(c);
+                if (c >= a.n_chunks) {
+                    queue_open = false;
+                    break;
+                }
+                const ChunkDev ch = a.chunks[c];
+                c_seg = wave_uniform(ch.seg);
+                c_next = wave_uniform(ch.first);
+                c_end = c_next + wave_uniform(ch.count);
+            }
+            const SegmentDev sg = a.segs[c_seg];
+            const uint32_t avail = c_end - c_next;
+            const uint32_t rank = lane_rank(need);
+            if (!active && rank < avail) {
+                const JobDev<R>& J = a.jobs[sg.job];
+                seg = c_seg;
+                pid = c_next + rank;
+                job = sg.job;
+                bin = sg.bin;
+                out = sg.out_offset + pid;
+                s.r = J.r0;
+                s.th = (R)J.th0;
+                s.ph = (R)J.ph0;
+                s.P = sg.P0;
+                s.t = 0.0;
+                s.n = 0u;
+                active = true;
+            }
+            const uint32_t cnt = (uint32_t)__popcll(need);
+            c_next += cnt < avail ? cnt : avail;
+            need = __ballot(!active);
+        }
+        if (!__any(active)) {
+            // hand back the unissued rest of this wave's chunk
+            if (c_next < c_end && lane == 0 && a.leftover != nullptr) {
+                const uint32_t slot = atomicAdd(a.leftover_count, 1u);
+                ChunkDev ch;
+                ch.seg = c_seg;
+                ch.first = c_next;
+                ch.count = c_end - c_next;
+                ch.pad0 = 0;
+                a.leftover[slot] = ch;
+            }
+            break;
+        }
+
+        if (active) {
+            const JobDev<R>& J = a.jobs[job];
+            uint32_t flags = 0;
+            bool done = false;
+            if (a.job_cancel != nullptr && a.job_cancel[job] != 0u) {
+                active = false;  // dropped: no record
+            } else if (s.n >= J.step_cap) {
+                flags = kFlagCapped;
+                done = true;
+            } else {
+                const RegionDev<R>* reg = a.regions + (size_t)job * kRegionStride;
+                if (M3D)
+                    step3d<R>(J, reg, s, pid, bin);
+                else
+                    step1d<R>(J, reg, s, pid, bin);
+                ++budget;
+                if (!(s.r == s.r) || !(s.P == s.P)) {
+                    flags = kFlagNaN;
+                    done = true;
+                } else if (s.r >= J.rb) {
+                    done = true;
+                }
+            }
+            if (done) {
+                a.exP[out] = s.P;
+                a.exT[out] = s.t;
+                a.exNF[out] = s.n | (flags << kFlagShift);
+                if (a.exR != nullptr) {
+                    a.exR[out] = s.r;
+                    a.exTh[out] = (double)s.th;
+                    a.exPh[out] = (double)s.ph;
+                }
+                if (a.job_done != nullptr) atomicAdd(&a.job_done[job], 1u);
+                active = false;
+            } else if (active && budget >= a.step_budget) {
+                // slice over: park the particle for the next launch
+                const uint32_t slot = atomicAdd(a.suspend_count, 1u);
+                SuspendDev q;
+                q.r = s.r;
+                q.P = s.P;
+                q.t = s.t;
+                q.th = (double)s.th;
+                q.ph = (double)s.ph;
+                q.n = s.n;
+                q.seg = seg;
+                q.pid = pid;
+                q.pad0 = 0;
+                a.suspend[slot] = q;
+                active = false;
+            }
+        }
+        // a wave stops taking work once one of its lanes used up the budget
+        if (a.step_budget != 0xffffffffu && __any(budget >= a.step_budget)) launch_open = false;
+    }
+}
+
+template <typename R, bool M3D>
+static hipError_t launch_prop(const PropArgs<R>& a, int grid, int block, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_propagate<R, M3D>), dim3(grid), dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_propagate_3d_mixed(const PropArgs<float>& a, int grid, int block, hipStream_t s)
+{
+    return launch_prop<float, true>(a, grid, block, s);
+}
+hipError_t launch_propagate_3d_fp64(const PropArgs<double>& a, int grid, int block, hipStream_t s)
+{
+    return launch_prop<double, true>(a, grid, block, s);
+}
+hipError_t launch_propagate_1d_mixed(const PropArgs<float>& a, int grid, int block, hipStream_t s)
+{
+    return launch_prop<float, false>(a, grid, block, s);
+}
+hipError_t launch_propagate_1d_fp64(const PropArgs<double>& a, int grid, int block, hipStream_t s)
+{
+    return launch_prop<double, false>(a, grid, block, s);
+}
+
+hipError_t occupancy_propagate(int model, int prec, int block, int* blocks_per_cu)
+{
+    const void* f = nullptr;
+    if (model == 1 && prec == 1) f = (const void*)&k_propagate<float, true>;
+    if (model == 1 && prec == 0) f = (const void*)&k_propagate<double, true>;
+    if (model == 0 && prec == 1) f = (const void*)&k_propagate<float, false>;
+    if (model == 0 && prec == 0) f = (const void*)&k_propagate<double, false>;
+    if (f == nullptr) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Per-bin reduction.
+// ---------------------------------------------------------------------------
+constexpr int kReduceBlock = 256;
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* sh)
+{
+    // fixed-order tree: wave shuffles, then the wave partials in LDS
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int wid = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[wid] = v;
+    __syncthreads();
+    T t = 0;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < kReduceBlock / 64; ++i) t += sh[i];
+        sh[0] = t;
+    }
+    __syncthreads();
+    t = sh[0];
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ double lis_weight(const LisDev& L, double P)
+{
+    // f_LIS(P) = J_LIS(P) / P^2
+    return L.norm * ::pow(P, -L.index) / (P * P);
+}
+
+__global__ void __launch_bounds__(kReduceBlock) k_reduce(const ReduceArgs a)
+{
+    __shared__ uint32_t hist[kNHist];
+    __shared__ double shd[kReduceBlock / 64];
+    __shared__ unsigned long long shu[kReduceBlock / 64];
+    const uint32_t sidx = a.seg_base + blockIdx.x;
+    const SegmentDev sg = a.segs[sidx];
+    const LisDev L = a.lis[sg.job];
+    for (int i = threadIdx.x; i < kNHist; i += kReduceBlock) hist[i] = 0u;
+    __syncthreads();
+    double sw = 0.0, st = 0.0;
+    unsigned long long sn = 0, ncap = 0, nnan = 0, nused = 0;
+    const double inv_p0 = 1.0 / sg.P0;
+    for (uint32_t i = threadIdx.x; i < sg.count; i += kReduceBlock) {
+        const uint32_t o = sg.out_offset + i;
+        const uint32_t nf = a.exNF[o];
+        const uint32_t fl = nf >> kFlagShift;
+        sn += nf & ((1u << kFlagShift) - 1u);
+        if (fl & kFlagCapped) {
+            ++ncap;
+            continue;
+        }
+        if (fl & kFlagNaN) {
+            ++nnan;
+            continue;
+        }
+        const double P = a.exP[o];
+        sw += lis_weight(L, P);
+        st += a.exT[o];
+        ++nused;
+        int j = (int)::floor(128.0 * ::log10(P * inv_p0) / 3.0);
+        j = j < 0 ? 0 : (j > 128 ? 128 : j);
+        atomicAdd(&hist[j], 1u);
+    }
+    const double SW = block_sum<double>(sw, shd);
+    const double ST = block_sum<double>(st, shd);
+    const unsigned long long SN = block_sum<unsigned long long>(sn, shu);
+    const unsigned long long NC = block_sum<unsigned long long>(ncap, shu);
+    const unsigned long long NN = block_sum<unsigned long long>(nnan, shu);
+    const unsigned long long NU = block_sum<unsigned long long>(nused, shu);
+    const double N = (double)NU;
+    const double mean = NU > 0 ? SW / N : 0.0;
+    double ss = 0.0;
+    if (NU > 1) {
+        for (uint32_t i = threadIdx.x; i < sg.count; i += kReduceBlock) {
+            const uint32_t o = sg.out_offset + i;
+            if ((a.exNF[o] >> kFlagShift) != 0u) continue;
+            const double dw = lis_weight(L, a.exP[o]) - mean;
+            ss += dw * dw;
+        }
+    }
+    const double SS = block_sum<double>(ss, shd);
+    __syncthreads();
+    const uint32_t ob = a.out_base + blockIdx.x;
+    if (a.hist != nullptr)
+        for (int i = threadIdx.x; i < kNHist; i += kReduceBlock)
+            a.hist[(size_t)ob * kNHist + i] = hist[i];
+    if (threadIdx.x == 0) {
+        const double p2 = sg.P0 * sg.P0;
+        if (a.flux) a.flux[ob] = p2 * mean;
+        if (a.flux_se) a.flux_se[ob] = NU > 1 ? p2 * ::sqrt(SS / (N - 1.0) / N) : 0.0;
+        if (a.mean_t) a.mean_t[ob] = NU > 0 ? ST / N : 0.0;
+        if (a.steps) a.steps[ob] = SN;
+        if (a.n_capped) a.n_capped[ob] = (uint32_t)NC;
+        if (a.n_nan) a.n_nan[ob] = (uint32_t)NN;
+    }
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, uint32_t n_segs, hipStream_t s)
+{
+    if (n_segs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce, dim3(n_segs), dim3(kReduceBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint32_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics.
+// ---------------------------------------------------------------------------
+__global__ void k_probe_rng(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
+                            uint32_t c3, uint32_t n, uint32_t* words, double* z64, float* z32)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4 x = philox4x32_10(k0, k1, c0 + i, c1, c2, c3);
+    if (words) {
+        words[4 * (size_t)i + 0] = x.x;
+        words[4 * (size_t)i + 1] = x.y;
+        words[4 * (size_t)i + 2] = x.z;
+        words[4 * (size_t)i + 3] = x.w;
+    }
+    if (z64) {
+        double z[3];
+        normals<double, 3>(k0, k1, c0 + i, c1, c2, c3, z);
+        for (int j = 0; j < 3; ++j) z64[3 * (size_t)i + j] = z[j];
+    }
+    if (z32) {
+        float z[3];
+        normals<float, 3>(k0, k1, c0 + i, c1, c2, c3, z);
+        for (int j = 0; j < 3; ++j) z32[3 * (size_t)i + j] = z[j];
+    }
+}
+
+hipError_t launch_probe_rng(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
+                            uint32_t c3, uint32_t n, uint32_t* words, double* z64, float* z32,
+                            hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe_rng, dim3((n + 255) / 256), dim3(256), 0, s, k0, k1, c0, c1, c2,
+                       c3, n, words, z64, z32);
+    return hipGetLastError();
+}
+
+template <typename R>
+__global__ void k_probe_coeffs(const JobDev<R>* job, const RegionDev<R>* reg, const double* pts,
+                               uint32_t n, double* out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const JobDev<R>& J = *job;
+    const double P = pts[4 * (size_t)i + 0], r = pts[4 * (size_t)i + 1];
+    const R th = (R)pts[4 * (size_t)i + 2], ph = (R)pts[4 * (size_t)i + 3];
+    Coef3<R> c;
+    coeffs3d<R, true>(J, reg[region_of(J, r)], r, P, th, ph, c);
+    double* o = out + (size_t)kProbeOut * i;
+    o[0] = c.Ar;
+    o[1] = c.At;
+    o[2] = c.Ap;
+    o[3] = c.AP;
+    o[4] = c.Brr;
+    o[5] = c.Bpr;
+    o[6] = c.Bpp;
+    o[7] = c.Btt;
+    o[8] = c.dt;
+    o[9] = c.Hw;
+    o[10] = c.vdr;
+    o[11] = c.vdt;
+    o[12] = c.vdp;
+    o[13] = c.Krr;
+    o[14] = c.Krp;
+    o[15] = c.kpar;
+}
+
+hipError_t launch_probe_coeffs_fp64(const JobDev<double>* job, const RegionDev<double>* reg,
+                                    const double* pts, uint32_t n, double* out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe_coeffs<double>, dim3((n + 63) / 64), dim3(64), 0, s, job, reg,
+                       pts, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_coeffs_mixed(const JobDev<float>* job, const RegionDev<float>* reg,
+                                     const double* pts, uint32_t n, double* out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe_coeffs<float>, dim3((n + 63) / 64), dim3(64), 0, s, job, reg, pts,
+                       n, out);
+    return hipGetLastError();
+}
+
+}  // namespace cosmica

@@ -1,0 +1,1656 @@
+// runtime.cpp -- host runtime of libcosmica: the C ABI of include/cosmica.h.
+//
+// Validation, unit conversion into device tables, the flat work index
+// (jobs x rigidity bins x particles, cut into refill chunks), persistent
+// launches, per-bin reduction, HIP-event timings, the launch-shape tuner and
+// the continuous-batching server.
+#include "cosmica.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "engine.hpp"
+
+using namespace cosmica;
+
+namespace {
+
+// Physical constants of the unit conversion (AU: IAU 2012).
+constexpr double kAuCm = 1.495978707e13;
+constexpr double kAuKm = 1.495978707e8;
+constexpr double kAuM = 1.495978707e11;
+constexpr double kLightMs = 299792458.0;
+constexpr double kPiH = 3.141592653589793238462643383279502884;
+constexpr uint32_t kDefaultStepCap = 10000000u;
+
+#define HIP_TRY(expr)                                        \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) {                              \
+            last_hip_error() = e_;                           \
+            return COSMICA_EDEVICE;                          \
+        }                                                    \
+    } while (0)
+
+hipError_t& last_hip_error()
+{
+    static thread_local hipError_t e = hipSuccess;
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// Validated, self-contained copy of a job.
+// ---------------------------------------------------------------------------
+struct JobCopy {
+    cosmica_helio helio;
+    cosmica_species species;
+    std::vector<double> rig;
+    std::vector<uint32_t> cnt;
+    uint64_t seed = 0;
+    uint32_t tag = 0;
+    uint32_t cap = kDefaultStepCap;
+    uint32_t bin_offset = 0;
+    uint64_t total = 0;
+};
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+cosmica_status validate(const cosmica_job* j)
+{
+    if (j == nullptr || j->helio == nullptr || j->species == nullptr) return COSMICA_EINVAL;
+    if (j->n_bins < 1 || j->rigidity_gv == nullptr || j->particles_per_bin == nullptr)
+        return COSMICA_EINVAL;
+    const cosmica_helio& h = *j->helio;
+    const cosmica_species& s = *j->species;
+    if (h.model != COSMICA_MODEL_1D && h.model != COSMICA_MODEL_3D) return COSMICA_EINVAL;
+    if (h.n_regions < 1 || h.n_regions > COSMICA_MAX_REGIONS) return COSMICA_EINVAL;
+    if (!finite_pos(h.r_boundary_au) || !finite_pos(h.r0_au) || !(h.r0_au < h.r_boundary_au))
+        return COSMICA_EINVAL;
+    if (!finite_pos(h.dt_max_s) || !finite_pos(h.dt_diff_frac)) return COSMICA_EINVAL;
+    if (!std::isfinite(h.dt_adv_frac) || h.dt_adv_frac < 0.0) return COSMICA_EINVAL;
+    if (h.drift != 0 && h.drift != 1) return COSMICA_EINVAL;
+    if (h.hcs != 0 && h.hcs != 1) return COSMICA_EINVAL;
+    if (h.hcs == 1 && h.drift != 1) return COSMICA_EINVAL;
+    if (h.polarity != 1 && h.polarity != -1) return COSMICA_EINVAL;
+    const bool drift = h.model == COSMICA_MODEL_3D && h.drift == 1;
+    for (int k = 0; k < h.n_regions; ++k) {
+        if (!finite_pos(h.kappa0_cm2_s[k])) return COSMICA_EINVAL;
+        if (!std::isfinite(h.v_slow_km_s[k]) || h.v_slow_km_s[k] < 0.0) return COSMICA_EINVAL;
+        if (drift && !(h.v_slow_km_s[k] > 0.0)) return COSMICA_EINVAL;
+        if (!std::isfinite(h.tilt_deg[k]) || h.tilt_deg[k] < 0.0 || !(h.tilt_deg[k] < 90.0))
+            return COSMICA_EINVAL;
+    }
+    if (h.model == COSMICA_MODEL_3D) {
+        if (!std::isfinite(h.v_fast_km_s) || h.v_fast_km_s < 0.0) return COSMICA_EINVAL;
+        if (drift && !(h.v_fast_km_s > 0.0)) return COSMICA_EINVAL;
+        if (!(h.theta0_rad > 0.0) || !(h.theta0_rad < kPiH)) return COSMICA_EINVAL;
+        if (!std::isfinite(h.phi0_rad)) return COSMICA_EINVAL;
+        if (!std::isfinite(h.omega_rad_s) || h.omega_rad_s < 0.0) return COSMICA_EINVAL;
+        if (!(h.kperp_over_kpar > 0.0) || !(h.kperp_over_kpar <= 1.0)) return COSMICA_EINVAL;
+        if (drift && (!finite_pos(h.b0_nT) || !finite_pos(h.v_ref_km_s))) return COSMICA_EINVAL;
+    }
+    if (!std::isfinite(s.mass_gev) || s.mass_gev < 0.0 || s.charge == 0) return COSMICA_EINVAL;
+    if (!finite_pos(s.lis_norm) || !std::isfinite(s.lis_index)) return COSMICA_EINVAL;
+    if (j->step_cap > COSMICA_MAX_STEP_CAP) return COSMICA_EINVAL;
+    uint64_t total = 0;
+    for (int b = 0; b < j->n_bins; ++b) {
+        if (!finite_pos(j->rigidity_gv[b])) return COSMICA_EINVAL;
+        if (j->particles_per_bin[b] < 1) return COSMICA_EINVAL;
+        total += j->particles_per_bin[b];
+    }
+    if (total >= (1ull << 32)) return COSMICA_EINVAL;
+    if ((uint64_t)j->bin_offset + (uint64_t)j->n_bins > (1ull << 32)) return COSMICA_EINVAL;
+    return COSMICA_OK;
+}
+
+JobCopy copy_job(const cosmica_job* j)
+{
+    JobCopy c;
+    c.helio = *j->helio;
+    c.species = *j->species;
+    c.rig.assign(j->rigidity_gv, j->rigidity_gv + j->n_bins);
+    c.cnt.assign(j->particles_per_bin, j->particles_per_bin + j->n_bins);
+    c.seed = j->seed;
+    c.tag = j->job_tag;
+    c.cap = j->step_cap == 0 ? kDefaultStepCap : j->step_cap;
+    c.bin_offset = j->bin_offset;
+    for (uint32_t n : c.cnt) c.total += n;
+    return c;
+}
+
+// Physical inputs -> device constants in AU, s, GV.
+template <typename R>
+void make_tables(const JobCopy& jc, JobDev<R>* J, RegionDev<R>* reg, LisDev* lis)
+{
+    const cosmica_helio& h = jc.helio;
+    const cosmica_species& s = jc.species;
+    std::memset(J, 0, sizeof(*J));
+    J->seed_lo = (uint32_t)(jc.seed & 0xffffffffu);
+    J->seed_hi = (uint32_t)(jc.seed >> 32);
+    J->job_tag = jc.tag;
+    J->step_cap = jc.cap;
+    J->nreg = h.n_regions;
+    J->drift = h.model == COSMICA_MODEL_3D ? h.drift : 0;
+    J->hcs = h.model == COSMICA_MODEL_3D ? h.hcs : 0;
+    J->rb = h.r_boundary_au;
+    J->inv_shell = (double)h.n_regions / h.r_boundary_au;
+    J->r0 = h.r0_au;
+    J->th0 = h.theta0_rad;
+    J->ph0 = h.phi0_rad;
+    J->vf = (R)(h.v_fast_km_s / kAuKm);
+    J->omega = (R)h.omega_rad_s;
+    J->kperp_frac = (R)h.kperp_over_kpar;
+    // |B| at 1 AU on the ecliptic is b0 for a wind of v_ref: B_r(1 AU) = b0 / sqrt(1 + Gamma_E^2)
+    double br0 = h.b0_nT;
+    if (h.v_ref_km_s > 0.0) {
+        const double gE = h.omega_rad_s * kAuKm / h.v_ref_km_s;
+        br0 = h.b0_nT / std::sqrt(1.0 + gE * gE);
+    }
+    J->br0 = (R)br0;
+    // kappa_A = beta P / (3 |B|) [GV, nT -> AU^2/s], |B| = br0 / r^2 * sqrt(1 + Gamma^2)
+    J->gcoef = br0 > 0.0 ? (R)(1e18 / (3.0 * br0 * kAuM * kAuM)) : (R)0;
+    J->rlcoef = (R)(1e18 / (kLightMs * kAuM));
+    J->abs_z = (R)std::fabs((double)s.charge);
+    J->mass2 = (R)(s.mass_gev * s.mass_gev);
+    J->sqA = (R)((s.charge > 0 ? 1.0 : -1.0) * (double)h.polarity);
+    J->dt_max = (R)h.dt_max_s;
+    J->diff_frac = (R)h.dt_diff_frac;
+    J->adv_frac = h.model == COSMICA_MODEL_3D ? (R)h.dt_adv_frac : (R)0;
+    for (int k = 0; k < kRegionStride; ++k) {
+        RegionDev<R>& g = reg[k];
+        std::memset(&g, 0, sizeof(g));
+        const int kk = k < h.n_regions ? k : h.n_regions - 1;
+        const double vs = h.v_slow_km_s[kk] / kAuKm;
+        const double alpha = h.tilt_deg[kk] * kPiH / 180.0;
+        g.k0 = (R)(h.kappa0_cm2_s[kk] / (kAuCm * kAuCm));
+        g.vs = (R)vs;
+        g.alpha = (R)alpha;
+        g.tana = (R)std::tan(alpha);
+        g.om_vs = vs > 0.0 ? (R)(h.omega_rad_s / vs) : (R)0;
+    }
+    lis->norm = s.lis_norm;
+    lis->index = s.lis_index;
+}
+
+// ---------------------------------------------------------------------------
+// Device memory accounted against the context budget.
+// ---------------------------------------------------------------------------
+struct Pool;
+
+}  // namespace
+
+struct Req;
+struct ServeGroup;
+
+struct cosmica_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint64_t budget = 0;
+    std::atomic<uint64_t> in_use{0};
+    int num_cus = 0;
+    std::string arch;
+    cosmica_launch launch[2][2];
+    cosmica_timings timings{};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // steps of the last execution: device array and its length
+    const uint64_t* last_steps = nullptr;
+    uint32_t last_nsteps = 0;
+    bool timings_pending = false;
+    // serving
+    std::mutex mu;
+    std::condition_variable cv;
+    std::thread worker;
+    bool stop = false;
+    bool worker_started = false;
+    uint64_t next_ticket = 1;
+    std::deque<Req*> queued;
+    std::map<uint64_t, std::unique_ptr<Req>> reqs;
+    std::unique_ptr<ServeGroup> groups[2][2];
+    hipStream_t serve_stream = nullptr;
+    cosmica_status serve_error = COSMICA_OK;
+    cosmica_ctx() = default;
+    ~cosmica_ctx();  // defined once the serving types are complete
+};
+
+namespace {
+
+cosmica_status dalloc(cosmica_ctx* ctx, size_t bytes, void** p)
+{
+    *p = nullptr;
+    if (bytes == 0) return COSMICA_OK;
+    bytes = (bytes + 255) & ~(size_t)255;
+    const uint64_t cur = ctx->in_use.fetch_add(bytes);
+    if (cur + bytes > ctx->budget) {
+        ctx->in_use.fetch_sub(bytes);
+        return COSMICA_ENOMEM;
+    }
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        ctx->in_use.fetch_sub(bytes);
+        *p = nullptr;
+        (void)hipGetLastError();
+        return COSMICA_ENOMEM;
+    }
+    return COSMICA_OK;
+}
+
+void dfree(cosmica_ctx* ctx, void* p, size_t bytes)
+{
+    if (p == nullptr) return;
+    bytes = (bytes + 255) & ~(size_t)255;
+    (void)hipFree(p);
+    ctx->in_use.fetch_sub(bytes);
+}
+
+// A set of device allocations freed together.
+struct DevSet {
+    cosmica_ctx* ctx = nullptr;
+    std::vector<std::pair<void*, size_t>> blocks;
+    explicit DevSet(cosmica_ctx* c) : ctx(c) {}
+    ~DevSet() { release(); }
+    void release()
+    {
+        for (auto& b : blocks) dfree(ctx, b.first, b.second);
+        blocks.clear();
+    }
+    template <typename T>
+    cosmica_status alloc(T** p, size_t n)
+    {
+        void* q = nullptr;
+        cosmica_status st = dalloc(ctx, n * sizeof(T), &q);
+        if (st != COSMICA_OK) return st;
+        if (q) blocks.emplace_back(q, n * sizeof(T));
+        *p = (T*)q;
+        return COSMICA_OK;
+    }
+};
+
+// Chunks of every segment of a model group, in the requested order.
+void make_chunks(const std::vector<SegmentDev>& segs, const std::vector<uint32_t>& seg_ids,
+                 int chunk, int order, std::vector<ChunkDev>* out)
+{
+    std::vector<uint32_t> ids = seg_ids;
+    if (order == 1)
+        std::stable_sort(ids.begin(), ids.end(),
+                         [&](uint32_t a, uint32_t b) { return segs[a].count > segs[b].count; });
+    const uint32_t c = (uint32_t)std::max(1, chunk);
+    for (uint32_t s : ids) {
+        for (uint32_t f = 0; f < segs[s].count; f += c) {
+            ChunkDev ch;
+            ch.seg = s;
+            ch.first = f;
+            ch.count = std::min(c, segs[s].count - f);
+            ch.pad0 = 0;
+            out->push_back(ch);
+        }
+    }
+}
+
+int grid_for(cosmica_ctx* ctx, int model, int prec, const cosmica_launch& L, uint64_t lanes_wanted)
+{
+    int occ = 0;
+    if (occupancy_propagate(model, prec, L.block, &occ) != hipSuccess || occ < 1) occ = 1;
+    int bpc = L.blocks_per_cu > 0 ? std::min(L.blocks_per_cu, occ) : occ;
+    uint64_t grid = (uint64_t)ctx->num_cus * (uint64_t)bpc;
+    const uint64_t need = (lanes_wanted + (uint64_t)L.block - 1) / (uint64_t)L.block;
+    if (need < grid) grid = std::max<uint64_t>(1, need);
+    return (int)grid;
+}
+
+bool launch_ok(const cosmica_launch& L)
+{
+    return (L.block == 64 || L.block == 128 || L.block == 256) &&
+           L.blocks_per_cu >= 0 && L.blocks_per_cu <= 32 && L.chunk >= 1 &&
+           (L.order == 0 || L.order == 1);
+}
+
+template <typename R>
+hipError_t launch_model(int model, const PropArgs<R>& a, int grid, int block, hipStream_t s);
+template <>
+hipError_t launch_model<float>(int model, const PropArgs<float>& a, int grid, int block,
+                               hipStream_t s)
+{
+    return model == 1 ? launch_propagate_3d_mixed(a, grid, block, s)
+                      : launch_propagate_1d_mixed(a, grid, block, s);
+}
+template <>
+hipError_t launch_model<double>(int model, const PropArgs<double>& a, int grid, int block,
+                                hipStream_t s)
+{
+    return model == 1 ? launch_propagate_3d_fp64(a, grid, block, s)
+                      : launch_propagate_1d_fp64(a, grid, block, s);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Plans.
+// ---------------------------------------------------------------------------
+struct cosmica_plan {
+    cosmica_ctx* ctx = nullptr;
+    int prec = 0;
+    bool want_exits = false;
+    std::vector<JobCopy> jobs;
+    std::vector<SegmentDev> segs;
+    std::vector<uint32_t> seg_first;  // first segment of each job
+    uint64_t total_particles = 0;
+    uint64_t model_particles[2] = {0, 0};
+    std::vector<ChunkDev> chunks_h[2];
+    DevSet mem;
+    void* jobs_d = nullptr;
+    void* regions_d = nullptr;
+    LisDev* lis_d = nullptr;
+    SegmentDev* segs_d = nullptr;
+    ChunkDev* chunks_d[2] = {nullptr, nullptr};
+    uint32_t* counters_d = nullptr;  // [head0, head1, resume_head, suspend_count, leftover_count]
+    double* exP = nullptr;
+    double* exT = nullptr;
+    uint32_t* exNF = nullptr;
+    double* exR = nullptr;
+    double* exTh = nullptr;
+    double* exPh = nullptr;
+    // plan-owned results
+    uint32_t* hist = nullptr;
+    double* flux = nullptr;
+    double* se = nullptr;
+    double* mt = nullptr;
+    uint64_t* steps = nullptr;
+    uint32_t* ncap = nullptr;
+    uint32_t* nnan = nullptr;
+    bool executed = false;
+    bool own_out = true;
+    explicit cosmica_plan(cosmica_ctx* c) : ctx(c), mem(c) {}
+};
+
+namespace {
+
+template <typename R>
+cosmica_status upload_tables(cosmica_plan* p)
+{
+    const size_t nj = p->jobs.size();
+    std::vector<JobDev<R>> jh(nj);
+    std::vector<RegionDev<R>> rh(nj * kRegionStride);
+    std::vector<LisDev> lh(nj);
+    for (size_t j = 0; j < nj; ++j)
+        make_tables<R>(p->jobs[j], &jh[j], &rh[j * kRegionStride], &lh[j]);
+    JobDev<R>* jd = nullptr;
+    RegionDev<R>* rd = nullptr;
+    cosmica_status st;
+    if ((st = p->mem.alloc(&jd, nj)) != COSMICA_OK) return st;
+    if ((st = p->mem.alloc(&rd, rh.size())) != COSMICA_OK) return st;
+    if ((st = p->mem.alloc(&p->lis_d, nj)) != COSMICA_OK) return st;
+    HIP_TRY(hipMemcpyAsync(jd, jh.data(), nj * sizeof(JobDev<R>), hipMemcpyHostToDevice,
+                           p->ctx->stream));
+    HIP_TRY(hipMemcpyAsync(rd, rh.data(), rh.size() * sizeof(RegionDev<R>),
+                           hipMemcpyHostToDevice, p->ctx->stream));
+    HIP_TRY(hipMemcpyAsync(p->lis_d, lh.data(), nj * sizeof(LisDev), hipMemcpyHostToDevice,
+                           p->ctx->stream));
+    p->jobs_d = jd;
+    p->regions_d = rd;
+    return COSMICA_OK;
+}
+
+template <typename R>
+cosmica_status execute_prop(cosmica_plan* p)
+{
+    cosmica_ctx* ctx = p->ctx;
+    for (int model = 0; model < 2; ++model) {
+        const uint32_t nch = (uint32_t)p->chunks_h[model].size();
+        if (nch == 0) continue;
+        const cosmica_launch& L = ctx->launch[model][p->prec];
+        PropArgs<R> a;
+        std::memset(&a, 0, sizeof(a));
+        a.jobs = (const JobDev<R>*)p->jobs_d;
+        a.regions = (const RegionDev<R>*)p->regions_d;
+        a.segs = p->segs_d;
+        a.chunks = p->chunks_d[model];
+        a.n_chunks = nch;
+        a.head = p->counters_d + model;
+        a.exP = p->exP;
+        a.exT = p->exT;
+        a.exNF = p->exNF;
+        a.exR = p->exR;
+        a.exTh = p->exTh;
+        a.exPh = p->exPh;
+        a.resume = nullptr;
+        a.n_resume = 0;
+        a.resume_head = p->counters_d + 2;
+        a.suspend = nullptr;
+        a.suspend_count = p->counters_d + 3;
+        a.step_budget = 0xffffffffu;
+        a.job_cancel = nullptr;
+        a.job_done = nullptr;
+        a.leftover = nullptr;
+        a.leftover_count = p->counters_d + 4;
+        const int grid = grid_for(ctx, model, p->prec, L, p->model_particles[model]);
+        ctx->timings.grid_blocks = grid;
+        ctx->timings.block = L.block;
+        HIP_TRY(launch_model<R>(model, a, grid, L.block, ctx->stream));
+    }
+    return COSMICA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cosmica_abi_version(void) { return COSMICA_ABI_VERSION; }
+
+const char* cosmica_strerror(cosmica_status s)
+{
+    switch (s) {
+    case COSMICA_OK: return "ok";
+    case COSMICA_EINVAL: return "invalid argument";
+    case COSMICA_ENOMEM: return "out of device memory or over the HBM budget";
+    case COSMICA_EDEVICE: return "HIP device error";
+    case COSMICA_EBUSY: return "serving queue full";
+    case COSMICA_ECANCELED: return "request cancelled";
+    case COSMICA_ESTEPCAP: return "some particles reached the step cap";
+    case COSMICA_ENOTFOUND: return "unknown ticket";
+    }
+    return "unknown status";
+}
+
+cosmica_status cosmica_validate_job(const cosmica_job* job) { return validate(job); }
+
+cosmica_status cosmica_create(cosmica_ctx** out, int device, uint64_t hbm_budget_bytes,
+                              void* hip_stream)
+{
+    if (out == nullptr) return COSMICA_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return COSMICA_EDEVICE;
+    }
+    if (device < 0 || device >= ndev) return COSMICA_EINVAL;
+    HIP_TRY(hipSetDevice(device));
+    auto ctx = std::make_unique<cosmica_ctx>();
+    ctx->device = device;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    ctx->num_cus = prop.multiProcessorCount;
+    ctx->arch = prop.gcnArchName;
+    size_t freeb = 0, totalb = 0;
+    HIP_TRY(hipMemGetInfo(&freeb, &totalb));
+    ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)freeb);
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+    } else {
+        HIP_TRY(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+        ctx->own_stream = true;
+    }
+    for (int i = 0; i < 4; ++i) HIP_TRY(hipEventCreate(&ctx->ev[i]));
+    for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 2; ++q) ctx->launch[m][q] = cosmica_launch{256, 0, 256, 0};
+    *out = ctx.release();
+    return COSMICA_OK;
+}
+
+cosmica_status cosmica_plan_create(cosmica_ctx* ctx, const cosmica_job* jobs, int32_t n_jobs,
+                                   cosmica_precision precision, int32_t want_exits,
+                                   cosmica_plan** out)
+{
+    if (ctx == nullptr || out == nullptr || jobs == nullptr || n_jobs < 1) return COSMICA_EINVAL;
+    if (precision != COSMICA_PREC_FP64 && precision != COSMICA_PREC_MIXED) return COSMICA_EINVAL;
+    *out = nullptr;
+    uint64_t total = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        if (validate(&jobs[j]) != COSMICA_OK) return COSMICA_EINVAL;
+        for (int b = 0; b < jobs[j].n_bins; ++b) total += jobs[j].particles_per_bin[b];
+    }
+    if (total >= (1ull << 32)) return COSMICA_EINVAL;
+    HIP_TRY(hipSetDevice(ctx->device));
+    auto p = std::make_unique<cosmica_plan>(ctx);
+    p->prec = precision;
+    p->want_exits = want_exits != 0;
+    p->total_particles = total;
+    std::vector<uint32_t> ids[2];
+    uint32_t off = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        p->jobs.push_back(copy_job(&jobs[j]));
+        const JobCopy& jc = p->jobs.back();
+        const int model = jc.helio.model;
+        p->seg_first.push_back((uint32_t)p->segs.size());
+        for (size_t b = 0; b < jc.rig.size(); ++b) {
+            SegmentDev s;
+            std::memset(&s, 0, sizeof(s));
+            s.P0 = jc.rig[b];
+            s.job = (uint32_t)j;
+            s.bin = jc.bin_offset + (uint32_t)b;
+            s.count = jc.cnt[b];
+            s.out_offset = off;
+            off += jc.cnt[b];
+            ids[model].push_back((uint32_t)p->segs.size());
+            p->model_particles[model] += jc.cnt[b];
+            p->segs.push_back(s);
+        }
+    }
+    for (int m = 0; m < 2; ++m) {
+        const cosmica_launch& L = ctx->launch[m][precision];
+        make_chunks(p->segs, ids[m], L.chunk, L.order, &p->chunks_h[m]);
+    }
+    cosmica_status st = precision == COSMICA_PREC_MIXED ? upload_tables<float>(p.get())
+                                                         : upload_tables<double>(p.get());
+    if (st != COSMICA_OK) return st;
+    const size_t ns = p->segs.size();
+    if ((st = p->mem.alloc(&p->segs_d, ns)) != COSMICA_OK) return st;
+    for (int m = 0; m < 2; ++m)
+        if (!p->chunks_h[m].empty() &&
+            (st = p->mem.alloc(&p->chunks_d[m], p->chunks_h[m].size())) != COSMICA_OK)
+            return st;
+    if ((st = p->mem.alloc(&p->counters_d, 8)) != COSMICA_OK) return st;
+    if ((st = p->mem.alloc(&p->exP, total)) != COSMICA_OK) return st;
+    if ((st = p->mem.alloc(&p->exT, total)) != COSMICA_OK) return st;
+    if ((st = p->mem.alloc(&p->exNF, total)) != COSMICA_OK) return st;
+    if (p->want_exits) {
+        if ((st = p->mem.alloc(&p->exR, total)) != COSMICA_OK) return st;
+        if ((st = p->mem.alloc(&p->exTh, total)) != COSMICA_OK) return st;
+        if ((st = p->mem.alloc(&p->exPh, total)) != COSMICA_OK) return st;
+    }
+    if ((st = p->mem.alloc(&p->hist, ns * kNHist)) != COSMICA_OK) return st;
+    if ((st = p->mem.alloc(&p->flux, ns)) != COSMICA_OK) return st;
+    if ((st = p->mem.alloc(&p->se, ns)) != COSMICA_OK) return st;
+    if ((st = p->mem.alloc(&p->mt, ns)) != COSMICA_OK) return st;
+    if ((st = p->mem.alloc(&p->steps, ns)) != COSMICA_OK) return st;
+    if ((st = p->mem.alloc(&p->ncap, ns)) != COSMICA_OK) return st;
+    if ((st = p->mem.alloc(&p->nnan, ns)) != COSMICA_OK) return st;
+    HIP_TRY(hipMemcpyAsync(p->segs_d, p->segs.data(), ns * sizeof(SegmentDev),
+                           hipMemcpyHostToDevice, ctx->stream));
+    for (int m = 0; m < 2; ++m)
+        if (!p->chunks_h[m].empty())
+            HIP_TRY(hipMemcpyAsync(p->chunks_d[m], p->chunks_h[m].data(),
+                                   p->chunks_h[m].size() * sizeof(ChunkDev),
+                                   hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    *out = p.release();
+    return COSMICA_OK;
+}
+
+cosmica_status cosmica_plan_execute(cosmica_plan* p, const cosmica_bins_dev* out)
+{
+    if (p == nullptr) return COSMICA_EINVAL;
+    cosmica_ctx* ctx = p->ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipEventRecord(ctx->ev[0], ctx->stream));
+    HIP_TRY(launch_fill_u32(p->counters_d, 0u, 8, ctx->stream));
+    cosmica_status st = p->prec == COSMICA_PREC_MIXED ? execute_prop<float>(p)
+                                                       : execute_prop<double>(p);
+    if (st != COSMICA_OK) return st;
+    HIP_TRY(hipEventRecord(ctx->ev[1], ctx->stream));
+    ReduceArgs r;
+    std::memset(&r, 0, sizeof(r));
+    r.segs = p->segs_d;
+    r.lis = p->lis_d;
+    r.exP = p->exP;
+    r.exT = p->exT;
+    r.exNF = p->exNF;
+    r.seg_base = 0;
+    r.out_base = 0;
+    if (out == nullptr) {
+        r.hist = p->hist;
+        r.flux = p->flux;
+        r.flux_se = p->se;
+        r.mean_t = p->mt;
+        r.steps = p->steps;
+        r.n_capped = p->ncap;
+        r.n_nan = p->nnan;
+    } else {
+        r.hist = out->hist;
+        r.flux = out->flux;
+        r.flux_se = out->flux_se;
+        r.mean_t = out->mean_exit_time_s;
+        r.steps = out->steps ? out->steps : p->steps;
+        r.n_capped = out->n_capped;
+        r.n_nan = out->n_nan;
+    }
+    HIP_TRY(launch_reduce(r, (uint32_t)p->segs.size(), ctx->stream));
+    HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
+    p->executed = true;
+    p->own_out = out == nullptr;
+    ctx->last_steps = r.steps;
+    ctx->last_nsteps = (uint32_t)p->segs.size();
+    ctx->timings_pending = true;
+    ctx->timings.particles = p->total_particles;
+    ctx->timings.upload_ms = 0.0;
+    ctx->timings.download_ms = 0.0;
+    return COSMICA_OK;
+}
+
+static cosmica_status finish_timings(cosmica_ctx* ctx)
+{
+    if (!ctx->timings_pending) return COSMICA_OK;
+    HIP_TRY(hipEventSynchronize(ctx->ev[2]));
+    float a = 0.f, b = 0.f;
+    HIP_TRY(hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));
+    HIP_TRY(hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
+    ctx->timings.propagate_ms = a;
+    ctx->timings.reduce_ms = b;
+    if (ctx->last_steps && ctx->last_nsteps) {
+        std::vector<uint64_t> s(ctx->last_nsteps);
+        HIP_TRY(hipMemcpy(s.data(), ctx->last_steps, s.size() * sizeof(uint64_t),
+                          hipMemcpyDeviceToHost));
+        uint64_t t = 0;
+        for (uint64_t v : s) t += v;
+        ctx->timings.steps = t;
+    }
+    ctx->timings_pending = false;
+    return COSMICA_OK;
+}
+
+cosmica_status cosmica_plan_read(cosmica_plan* p, cosmica_result* results)
+{
+    if (p == nullptr || results == nullptr) return COSMICA_EINVAL;
+    if (!p->executed || !p->own_out) return COSMICA_EINVAL;
+    cosmica_ctx* ctx = p->ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    cosmica_status st = finish_timings(ctx);
+    if (st != COSMICA_OK) return st;
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t ns = p->segs.size();
+    std::vector<uint32_t> hist(ns * kNHist), ncap(ns), nnan(ns);
+    std::vector<double> flux(ns), se(ns), mt(ns);
+    std::vector<uint64_t> steps(ns);
+    HIP_TRY(hipMemcpy(hist.data(), p->hist, hist.size() * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(flux.data(), p->flux, ns * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(se.data(), p->se, ns * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(mt.data(), p->mt, ns * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(steps.data(), p->steps, ns * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ncap.data(), p->ncap, ns * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(nnan.data(), p->nnan, ns * 4, hipMemcpyDeviceToHost));
+    bool capped = false;
+    bool need_exits = false;
+    for (size_t j = 0; j < p->jobs.size(); ++j) need_exits |= results[j].exits != nullptr;
+    std::vector<double> eP, eT, eR, eTh, ePh;
+    std::vector<uint32_t> eNF;
+    if (need_exits) {
+        const size_t n = p->total_particles;
+        eP.resize(n);
+        eT.resize(n);
+        eNF.resize(n);
+        HIP_TRY(hipMemcpy(eP.data(), p->exP, n * 8, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(eT.data(), p->exT, n * 8, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(eNF.data(), p->exNF, n * 4, hipMemcpyDeviceToHost));
+        if (p->want_exits) {
+            eR.resize(n);
+            eTh.resize(n);
+            ePh.resize(n);
+            HIP_TRY(hipMemcpy(eR.data(), p->exR, n * 8, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(eTh.data(), p->exTh, n * 8, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(ePh.data(), p->exPh, n * 8, hipMemcpyDeviceToHost));
+        }
+    }
+    for (size_t j = 0; j < p->jobs.size(); ++j) {
+        const cosmica_result& R = results[j];
+        const uint32_t s0 = p->seg_first[j];
+        const size_t nb = p->jobs[j].rig.size();
+        for (size_t b = 0; b < nb; ++b) {
+            const size_t s = s0 + b;
+            if (R.hist) std::memcpy(R.hist + b * kNHist, &hist[s * kNHist], kNHist * 4);
+            if (R.flux) R.flux[b] = flux[s];
+            if (R.flux_se) R.flux_se[b] = se[s];
+            if (R.mean_exit_time_s) R.mean_exit_time_s[b] = mt[s];
+            if (R.steps) R.steps[b] = steps[s];
+            if (R.n_capped) R.n_capped[b] = ncap[s];
+            if (R.n_nan) R.n_nan[b] = nnan[s];
+            capped |= ncap[s] > 0;
+        }
+        if (R.exits) {
+            const uint32_t base = p->segs[s0].out_offset;
+            for (uint64_t i = 0; i < p->jobs[j].total; ++i) {
+                cosmica_exit& e = R.exits[i];
+                const size_t o = base + i;
+                e.P = eP[o];
+                e.t = eT[o];
+                e.n = eNF[o] & ((1u << kFlagShift) - 1u);
+                e.flags = eNF[o] >> kFlagShift;
+                e.r = p->want_exits ? eR[o] : 0.0;
+                e.theta = p->want_exits ? eTh[o] : 0.0;
+                e.phi = p->want_exits ? ePh[o] : 0.0;
+            }
+        }
+    }
+    ctx->timings.download_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return capped ? COSMICA_ESTEPCAP : COSMICA_OK;
+}
+
+cosmica_status cosmica_plan_info(const cosmica_plan* p, uint64_t* total_bins,
+                                 uint64_t* total_particles, int32_t* n_jobs)
+{
+    if (p == nullptr) return COSMICA_EINVAL;
+    if (total_bins) *total_bins = p->segs.size();
+    if (total_particles) *total_particles = p->total_particles;
+    if (n_jobs) *n_jobs = (int32_t)p->jobs.size();
+    return COSMICA_OK;
+}
+
+void cosmica_plan_destroy(cosmica_plan* p)
+{
+    if (p == nullptr) return;
+    (void)hipSetDevice(p->ctx->device);
+    (void)hipStreamSynchronize(p->ctx->stream);
+    if (p->ctx->last_nsteps && (p->ctx->last_steps == p->steps)) {
+        (void)finish_timings(p->ctx);
+        p->ctx->last_steps = nullptr;
+        p->ctx->last_nsteps = 0;
+    }
+    delete p;
+}
+
+cosmica_status cosmica_run(cosmica_ctx* ctx, const cosmica_job* jobs, int32_t n_jobs,
+                           cosmica_precision precision, cosmica_result* results)
+{
+    if (ctx == nullptr || jobs == nullptr || results == nullptr || n_jobs < 1)
+        return COSMICA_EINVAL;
+    bool want = false;
+    for (int j = 0; j < n_jobs; ++j) want |= results[j].exits != nullptr;
+    const auto t0 = std::chrono::steady_clock::now();
+    cosmica_plan* p = nullptr;
+    cosmica_status st = cosmica_plan_create(ctx, jobs, n_jobs, precision, want ? 1 : 0, &p);
+    if (st != COSMICA_OK) return st;
+    const double up =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    st = cosmica_plan_execute(p, nullptr);
+    if (st == COSMICA_OK) {
+        st = cosmica_plan_read(p, results);
+        ctx->timings.upload_ms = up;
+    }
+    cosmica_plan_destroy(p);
+    return st;
+}
+
+cosmica_status cosmica_set_launch(cosmica_ctx* ctx, cosmica_model model,
+                                  cosmica_precision precision, const cosmica_launch* cfg)
+{
+    if (ctx == nullptr || cfg == nullptr || (model != 0 && model != 1) ||
+        (precision != 0 && precision != 1) || !launch_ok(*cfg))
+        return COSMICA_EINVAL;
+    ctx->launch[model][precision] = *cfg;
+    return COSMICA_OK;
+}
+
+cosmica_status cosmica_get_launch(cosmica_ctx* ctx, cosmica_model model,
+                                  cosmica_precision precision, cosmica_launch* cfg)
+{
+    if (ctx == nullptr || cfg == nullptr || (model != 0 && model != 1) ||
+        (precision != 0 && precision != 1))
+        return COSMICA_EINVAL;
+    *cfg = ctx->launch[model][precision];
+    return COSMICA_OK;
+}
+
+cosmica_status cosmica_get_timings(cosmica_ctx* ctx, cosmica_timings* out)
+{
+    if (ctx == nullptr || out == nullptr) return COSMICA_EINVAL;
+    HIP_TRY(hipSetDevice(ctx->device));
+    cosmica_status st = finish_timings(ctx);
+    if (st != COSMICA_OK) return st;
+    *out = ctx->timings;
+    return COSMICA_OK;
+}
+
+cosmica_status cosmica_probe_rng(cosmica_ctx* ctx, uint64_t seed, uint32_t c0, uint32_t c1,
+                                 uint32_t c2, uint32_t c3, uint32_t n, uint32_t* words,
+                                 double* z64, float* z32)
+{
+    if (ctx == nullptr || n == 0) return COSMICA_EINVAL;
+    HIP_TRY(hipSetDevice(ctx->device));
+    DevSet m(ctx);
+    uint32_t* w = nullptr;
+    double* a = nullptr;
+    float* b = nullptr;
+    cosmica_status st;
+    if (words && (st = m.alloc(&w, 4 * (size_t)n)) != COSMICA_OK) return st;
+    if (z64 && (st = m.alloc(&a, 3 * (size_t)n)) != COSMICA_OK) return st;
+    if (z32 && (st = m.alloc(&b, 3 * (size_t)n)) != COSMICA_OK) return st;
+    HIP_TRY(launch_probe_rng((uint32_t)seed, (uint32_t)(seed >> 32), c0, c1, c2, c3, n, w, a, b,
+                             ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (words) HIP_TRY(hipMemcpy(words, w, 16 * (size_t)n, hipMemcpyDeviceToHost));
+    if (z64) HIP_TRY(hipMemcpy(z64, a, 24 * (size_t)n, hipMemcpyDeviceToHost));
+    if (z32) HIP_TRY(hipMemcpy(z32, b, 12 * (size_t)n, hipMemcpyDeviceToHost));
+    return COSMICA_OK;
+}
+
+cosmica_status cosmica_probe_coeffs(cosmica_ctx* ctx, const cosmica_job* job,
+                                    cosmica_precision precision, uint32_t n, const double* pts,
+                                    double* out)
+{
+    if (ctx == nullptr || pts == nullptr || out == nullptr || n == 0) return COSMICA_EINVAL;
+    if (validate(job) != COSMICA_OK || job->helio->model != COSMICA_MODEL_3D) return COSMICA_EINVAL;
+    if (precision != COSMICA_PREC_FP64 && precision != COSMICA_PREC_MIXED) return COSMICA_EINVAL;
+    for (uint32_t i = 0; i < n; ++i) {
+        const double* q = pts + 4 * (size_t)i;
+        if (!finite_pos(q[0]) || !finite_pos(q[1]) || !(q[2] > 0.0) || !(q[2] < kPiH) ||
+            !std::isfinite(q[3]))
+            return COSMICA_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    const JobCopy jc = copy_job(job);
+    DevSet m(ctx);
+    double* pd = nullptr;
+    double* od = nullptr;
+    cosmica_status st;
+    if ((st = m.alloc(&pd, 4 * (size_t)n)) != COSMICA_OK) return st;
+    if ((st = m.alloc(&od, (size_t)kProbeOut * n)) != COSMICA_OK) return st;
+    HIP_TRY(hipMemcpy(pd, pts, 32 * (size_t)n, hipMemcpyHostToDevice));
+    LisDev lis;
+    if (precision == COSMICA_PREC_FP64) {
+        JobDev<double> J;
+        std::vector<RegionDev<double>> R(kRegionStride);
+        make_tables<double>(jc, &J, R.data(), &lis);
+        JobDev<double>* jd = nullptr;
+        RegionDev<double>* rd = nullptr;
+        if ((st = m.alloc(&jd, 1)) != COSMICA_OK) return st;
+        if ((st = m.alloc(&rd, kRegionStride)) != COSMICA_OK) return st;
+        HIP_TRY(hipMemcpy(jd, &J, sizeof(J), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(rd, R.data(), R.size() * sizeof(R[0]), hipMemcpyHostToDevice));
+        HIP_TRY(launch_probe_coeffs_fp64(jd, rd, pd, n, od, ctx->stream));
+    } else {
+        JobDev<float> J;
+        std::vector<RegionDev<float>> R(kRegionStride);
+        make_tables<float>(jc, &J, R.data(), &lis);
+        JobDev<float>* jd = nullptr;
+        RegionDev<float>* rd = nullptr;
+        if ((st = m.alloc(&jd, 1)) != COSMICA_OK) return st;
+        if ((st = m.alloc(&rd, kRegionStride)) != COSMICA_OK) return st;
+        HIP_TRY(hipMemcpy(jd, &J, sizeof(J), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(rd, R.data(), R.size() * sizeof(R[0]), hipMemcpyHostToDevice));
+        HIP_TRY(launch_probe_coeffs_mixed(jd, rd, pd, n, od, ctx->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipMemcpy(out, od, 8 * (size_t)kProbeOut * n, hipMemcpyDeviceToHost));
+    return COSMICA_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Launch-shape tuner: the warps-per-block sweep of the paper (Sec. VI,
+// Version 2) widened to workgroup size, resident workgroups per CU and the
+// refill chunk, timed on a calibration batch.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Calib {
+    cosmica_helio helio;
+    cosmica_species species;
+    std::vector<double> rig;
+    std::vector<uint32_t> cnt;
+    cosmica_job job;
+};
+
+void make_calibration(int model, uint32_t per_bin, Calib* c)
+{
+    std::memset(&c->helio, 0, sizeof(c->helio));
+    cosmica_helio& h = c->helio;
+    h.model = model;
+    h.n_regions = model == 1 ? 15 : 1;
+    for (int k = 0; k < h.n_regions; ++k) {
+        // a smooth, deterministic spread of shell parameters
+        h.kappa0_cm2_s[k] = 1.0e22 + 1.0e21 * (double)(k % 7);
+        h.v_slow_km_s[k] = 380.0 + 20.0 * (double)(k % 5);
+        h.tilt_deg[k] = 15.0 + 3.0 * (double)k;
+    }
+    h.v_fast_km_s = 760.0;
+    h.r_boundary_au = model == 1 ? 120.0 : 100.0;
+    h.r0_au = 1.0;
+    h.theta0_rad = 0.5 * kPiH;
+    h.phi0_rad = 0.0;
+    h.b0_nT = 5.0;
+    h.v_ref_km_s = 400.0;
+    h.omega_rad_s = 2.66e-6;
+    h.kperp_over_kpar = model == 1 ? 0.02 : 1.0;
+    h.polarity = 1;
+    h.drift = model == 1 ? 1 : 0;
+    h.hcs = model == 1 ? 1 : 0;
+    h.dt_max_s = 5e4;
+    h.dt_diff_frac = 0.02;
+    h.dt_adv_frac = model == 1 ? 0.1 : 0.0;
+    c->species = cosmica_species{0.93827208816, 1, 1, 1.9e4, 2.78};
+    const int nb = 16;
+    c->rig.resize(nb);
+    c->cnt.assign(nb, per_bin);
+    for (int b = 0; b < nb; ++b) c->rig[b] = 0.1 * std::pow(1000.0, (double)b / (nb - 1));
+    c->job = cosmica_job{&c->helio, &c->species, c->rig.data(), c->cnt.data(), nb, 0u, 12345ull,
+                         0u, 0u};  // tag 0, seed 12345, default cap, bin offset 0
+}
+
+std::string tune_key(cosmica_ctx* ctx, int model, int prec)
+{
+    std::string a = ctx->arch;
+    for (char& ch : a)
+        if (ch == ' ') ch = '_';
+    return a + " " + std::to_string(model) + " " + std::to_string(prec);
+}
+
+bool cache_lookup(const char* path, const std::string& key, cosmica_launch* L)
+{
+    if (path == nullptr) return false;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string arch;
+        int m, q;
+        cosmica_launch c;
+        double rate;
+        if (!(is >> arch >> m >> q >> c.block >> c.blocks_per_cu >> c.chunk >> c.order >> rate))
+            continue;
+        if (arch + " " + std::to_string(m) + " " + std::to_string(q) == key && launch_ok(c)) {
+            *L = c;
+            return true;
+        }
+    }
+    return false;
+}
+
+void cache_store(const char* path, const std::string& key, const cosmica_launch& L, double rate)
+{
+    if (path == nullptr) return;
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(path);
+        std::string line;
+        while (std::getline(f, line)) {
+            std::istringstream is(line);
+            std::string arch;
+            int m, q;
+            if (!(is >> arch >> m >> q)) continue;
+            if (arch + " " + std::to_string(m) + " " + std::to_string(q) != key)
+                keep.push_back(line);
+        }
+    }
+    std::ofstream f(path, std::ios::trunc);
+    for (auto& l : keep) f << l << "\n";
+    f << key << " " << L.block << " " << L.blocks_per_cu << " " << L.chunk << " " << L.order
+      << " " << rate << "\n";
+}
+
+}  // namespace
+
+extern "C" cosmica_status cosmica_tune(cosmica_ctx* ctx, cosmica_model model,
+                                       cosmica_precision precision, const char* cache_path)
+{
+    if (ctx == nullptr || (model != 0 && model != 1) || (precision != 0 && precision != 1))
+        return COSMICA_EINVAL;
+    const std::string key = tune_key(ctx, model, precision);
+    cosmica_launch L;
+    if (cache_lookup(cache_path, key, &L)) {
+        ctx->launch[model][precision] = L;
+        return COSMICA_OK;
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    // about four resident waves' worth of particles per SIMD at the default shape
+    const uint64_t lanes = (uint64_t)ctx->num_cus * 4 * 64 * 8;
+    Calib cal;
+    make_calibration(model, (uint32_t)std::max<uint64_t>(64, 2 * lanes / 16), &cal);
+    const int blocks[] = {64, 128, 256};
+    const int chunks[] = {64, 256, 1024};
+    cosmica_launch best = ctx->launch[model][precision];
+    double best_rate = -1.0;
+    const cosmica_launch saved = ctx->launch[model][precision];
+    for (int blk : blocks) {
+        int occ = 0;
+        if (occupancy_propagate(model, precision, blk, &occ) != hipSuccess || occ < 1) continue;
+        std::vector<int> bpcs = {0};
+        if (occ >= 2) bpcs.push_back(std::max(1, occ / 2));
+        for (int bpc : bpcs) {
+            for (int ch : chunks) {
+                cosmica_launch c{blk, bpc, ch, 1};
+                ctx->launch[model][precision] = c;
+                cosmica_plan* p = nullptr;
+                cosmica_status st = cosmica_plan_create(ctx, &cal.job, 1, precision, 0, &p);
+                if (st != COSMICA_OK) {
+                    ctx->launch[model][precision] = saved;
+                    return st;
+                }
+                double rate = 0.0;
+                for (int rep = 0; rep < 2 && st == COSMICA_OK; ++rep) {
+                    st = cosmica_plan_execute(p, nullptr);
+                    cosmica_timings t;
+                    if (st == COSMICA_OK) st = cosmica_get_timings(ctx, &t);
+                    if (st == COSMICA_OK && rep == 1 && t.propagate_ms > 0.0)
+                        rate = (double)t.steps / (t.propagate_ms * 1e-3);
+                }
+                cosmica_plan_destroy(p);
+                if (st != COSMICA_OK) {
+                    ctx->launch[model][precision] = saved;
+                    return st;
+                }
+                if (rate > best_rate) {
+                    best_rate = rate;
+                    best = c;
+                }
+            }
+        }
+    }
+    ctx->launch[model][precision] = best;
+    cache_store(cache_path, key, best, best_rate);
+    return COSMICA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Serving: continuous batching over bounded slices of the persistent kernel.
+// Requests are admitted while their exit records fit in the device pool; the
+// particles of every admitted request share the same launches, and particles
+// still inside at the end of a slice are parked (bit-exact) and resumed first
+// in the next one.
+// ---------------------------------------------------------------------------
+struct Req {
+    uint64_t ticket = 0;
+    JobCopy job;
+    int prec = 0;
+    int model = 0;
+    cosmica_result res{};
+    int state = 0;  // 0 queued, 1 resident, 2 done
+    cosmica_status status = COSMICA_OK;
+    bool cancel = false;
+    bool cancel_sent = false;
+    int slot = -1;
+    uint64_t ex0 = 0;
+};
+
+struct ServeGroup {
+    static constexpr uint32_t kSlots = 256;
+    static constexpr uint32_t kBinsPerSlot = 64;
+    int model = 0, prec = 0;
+    cosmica_ctx* ctx = nullptr;
+    DevSet mem;
+    void* jobs_d = nullptr;
+    void* regions_d = nullptr;
+    LisDev* lis_d = nullptr;
+    uint32_t* cancel_d = nullptr;
+    uint32_t* done_d = nullptr;
+    SegmentDev* segs_d = nullptr;
+    ChunkDev* chunks_d = nullptr;
+    uint32_t chunks_cap = 0;
+    void* chunks_block = nullptr;
+    uint64_t pool_cap = 0;
+    double* exP = nullptr;
+    double* exT = nullptr;
+    uint32_t* exNF = nullptr;
+    SuspendDev* susp[2] = {nullptr, nullptr};
+    uint32_t susp_cap = 0;
+    int cur = 0;
+    uint32_t n_resume = 0;
+    ChunkDev* left_d = nullptr;
+    uint32_t left_cap = 0;
+    uint32_t* counters_d = nullptr;  // head, resume_head, suspend_count, leftover_count
+    uint32_t* r_hist = nullptr;
+    double* r_flux = nullptr;
+    double* r_se = nullptr;
+    double* r_mt = nullptr;
+    uint64_t* r_steps = nullptr;
+    uint32_t* r_ncap = nullptr;
+    uint32_t* r_nnan = nullptr;
+    std::vector<int> free_slots;
+    std::vector<SegmentDev> segs_h;
+    std::map<uint64_t, uint64_t> free_ranges;  // offset -> length of free pool ranges
+    std::vector<ChunkDev> carry;               // chunks to hand to the next slice
+    std::vector<Req*> resident;
+    std::vector<Req*> releasing;               // cancelled, freed after the next slice
+    int grid = 0, block = 256;
+    uint32_t n_chunks_last = 0;
+    explicit ServeGroup(cosmica_ctx* c) : ctx(c), mem(c) {}
+};
+
+cosmica_ctx::~cosmica_ctx() = default;
+
+namespace {
+
+uint32_t slice_steps()
+{
+    const char* e = std::getenv("COSMICA_SLICE_STEPS");
+    long v = e ? std::strtol(e, nullptr, 10) : 0;
+    return v > 0 ? (uint32_t)v : 2048u;
+}
+
+uint64_t pool_particles(cosmica_ctx* ctx)
+{
+    const char* e = std::getenv("COSMICA_SERVE_POOL");
+    long long v = e ? std::strtoll(e, nullptr, 10) : 0;
+    uint64_t want = v > 0 ? (uint64_t)v : (256ull << 20);
+    const uint64_t used = ctx->in_use.load();
+    const uint64_t room = ctx->budget > used + (512ull << 20) ? ctx->budget - used - (512ull << 20) : 0;
+    return std::min<uint64_t>(want, room / 20);
+}
+
+template <typename R>
+cosmica_status group_alloc_tables(ServeGroup* g)
+{
+    JobDev<R>* jd = nullptr;
+    RegionDev<R>* rd = nullptr;
+    cosmica_status st;
+    if ((st = g->mem.alloc(&jd, ServeGroup::kSlots)) != COSMICA_OK) return st;
+    if ((st = g->mem.alloc(&rd, (size_t)ServeGroup::kSlots * kRegionStride)) != COSMICA_OK)
+        return st;
+    g->jobs_d = jd;
+    g->regions_d = rd;
+    return COSMICA_OK;
+}
+
+cosmica_status group_create(cosmica_ctx* ctx, int model, int prec, ServeGroup** out)
+{
+    auto g = std::make_unique<ServeGroup>(ctx);
+    g->model = model;
+    g->prec = prec;
+    cosmica_status st = prec == 1 ? group_alloc_tables<float>(g.get())
+                                  : group_alloc_tables<double>(g.get());
+    if (st != COSMICA_OK) return st;
+    const uint32_t S = ServeGroup::kSlots, B = ServeGroup::kBinsPerSlot;
+    if ((st = g->mem.alloc(&g->lis_d, S)) != COSMICA_OK) return st;
+    if ((st = g->mem.alloc(&g->cancel_d, S)) != COSMICA_OK) return st;
+    if ((st = g->mem.alloc(&g->done_d, S)) != COSMICA_OK) return st;
+    if ((st = g->mem.alloc(&g->segs_d, (size_t)S * B)) != COSMICA_OK) return st;
+    const cosmica_launch& L = ctx->launch[model][prec];
+    g->block = L.block;
+    g->grid = grid_for(ctx, model, prec, L, ~0ull >> 8);
+    g->susp_cap = (uint32_t)g->grid * (uint32_t)g->block;
+    if ((st = g->mem.alloc(&g->susp[0], g->susp_cap)) != COSMICA_OK) return st;
+    if ((st = g->mem.alloc(&g->susp[1], g->susp_cap)) != COSMICA_OK) return st;
+    g->left_cap = g->susp_cap / 64 + 64;
+    if ((st = g->mem.alloc(&g->left_d, g->left_cap)) != COSMICA_OK) return st;
+    if ((st = g->mem.alloc(&g->counters_d, 8)) != COSMICA_OK) return st;
+    if ((st = g->mem.alloc(&g->r_hist, (size_t)B * kNHist)) != COSMICA_OK) return st;
+    if ((st = g->mem.alloc(&g->r_flux, B)) != COSMICA_OK) return st;
+    if ((st = g->mem.alloc(&g->r_se, B)) != COSMICA_OK) return st;
+    if ((st = g->mem.alloc(&g->r_mt, B)) != COSMICA_OK) return st;
+    if ((st = g->mem.alloc(&g->r_steps, B)) != COSMICA_OK) return st;
+    if ((st = g->mem.alloc(&g->r_ncap, B)) != COSMICA_OK) return st;
+    if ((st = g->mem.alloc(&g->r_nnan, B)) != COSMICA_OK) return st;
+    g->pool_cap = pool_particles(ctx);
+    if (g->pool_cap < 1024) return COSMICA_ENOMEM;
+    if ((st = g->mem.alloc(&g->exP, g->pool_cap)) != COSMICA_OK) return st;
+    if ((st = g->mem.alloc(&g->exT, g->pool_cap)) != COSMICA_OK) return st;
+    if ((st = g->mem.alloc(&g->exNF, g->pool_cap)) != COSMICA_OK) return st;
+    g->free_ranges[0] = g->pool_cap;
+    for (int s = (int)S - 1; s >= 0; --s) g->free_slots.push_back(s);
+    g->segs_h.resize((size_t)S * B);
+    HIP_TRY(launch_fill_u32(g->cancel_d, 0u, S, ctx->serve_stream));
+    HIP_TRY(launch_fill_u32(g->done_d, 0u, S, ctx->serve_stream));
+    *out = g.release();
+    return COSMICA_OK;
+}
+
+bool pool_take(ServeGroup* g, uint64_t n, uint64_t* off)
+{
+    for (auto it = g->free_ranges.begin(); it != g->free_ranges.end(); ++it) {
+        if (it->second >= n) {
+            *off = it->first;
+            const uint64_t rest = it->second - n, start = it->first + n;
+            g->free_ranges.erase(it);
+            if (rest) g->free_ranges[start] = rest;
+            return true;
+        }
+    }
+    return false;
+}
+
+void pool_give(ServeGroup* g, uint64_t off, uint64_t n)
+{
+    auto it = g->free_ranges.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != g->free_ranges.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        g->free_ranges.erase(nx);
+    }
+    if (it != g->free_ranges.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            g->free_ranges.erase(it);
+        }
+    }
+}
+
+template <typename R>
+cosmica_status upload_slot(ServeGroup* g, Req* q)
+{
+    JobDev<R> J;
+    RegionDev<R> reg[kRegionStride];
+    LisDev lis;
+    make_tables<R>(q->job, &J, reg, &lis);
+    hipStream_t s = g->ctx->serve_stream;
+    const int slot = q->slot;
+    HIP_TRY(hipMemcpyAsync((JobDev<R>*)g->jobs_d + slot, &J, sizeof(J), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync((RegionDev<R>*)g->regions_d + (size_t)slot * kRegionStride, reg,
+                           sizeof(reg), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(g->lis_d + slot, &lis, sizeof(lis), hipMemcpyHostToDevice, s));
+    const size_t s0 = (size_t)slot * ServeGroup::kBinsPerSlot;
+    HIP_TRY(hipMemcpyAsync(g->segs_d + s0, &g->segs_h[s0],
+                           q->job.rig.size() * sizeof(SegmentDev), hipMemcpyHostToDevice, s));
+    // pageable host sources: wait so the staging copies are complete
+    HIP_TRY(hipStreamSynchronize(s));
+    return COSMICA_OK;
+}
+
+// Admit queued requests (FIFO) while a slot and a contiguous exit-record range fit.
+cosmica_status admit(cosmica_ctx* ctx)
+{
+    while (!ctx->queued.empty()) {
+        Req* q = ctx->queued.front();
+        if (q->cancel) {
+            ctx->queued.pop_front();
+            q->state = 2;
+            q->status = COSMICA_ECANCELED;
+            ctx->cv.notify_all();
+            continue;
+        }
+        std::unique_ptr<ServeGroup>& gp = ctx->groups[q->model][q->prec];
+        if (!gp) {
+            ServeGroup* g = nullptr;
+            cosmica_status st = group_create(ctx, q->model, q->prec, &g);
+            if (st != COSMICA_OK) return st;
+            gp.reset(g);
+        }
+        ServeGroup* g = gp.get();
+        if (g->free_slots.empty()) break;
+        uint64_t off = 0;
+        if (q->job.total > g->pool_cap) {  // can never fit
+            ctx->queued.pop_front();
+            q->state = 2;
+            q->status = COSMICA_ENOMEM;
+            ctx->cv.notify_all();
+            continue;
+        }
+        if (!pool_take(g, q->job.total, &off)) break;
+        ctx->queued.pop_front();
+        q->slot = g->free_slots.back();
+        g->free_slots.pop_back();
+        q->ex0 = off;
+        const size_t s0 = (size_t)q->slot * ServeGroup::kBinsPerSlot;
+        uint64_t o = off;
+        std::vector<uint32_t> ids;
+        for (size_t b = 0; b < q->job.rig.size(); ++b) {
+            SegmentDev& s = g->segs_h[s0 + b];
+            std::memset(&s, 0, sizeof(s));
+            s.P0 = q->job.rig[b];
+            s.job = (uint32_t)q->slot;
+            s.bin = q->job.bin_offset + (uint32_t)b;
+            s.count = q->job.cnt[b];
+            s.out_offset = (uint32_t)o;
+            o += q->job.cnt[b];
+            ids.push_back((uint32_t)(s0 + b));
+        }
+        const cosmica_launch& L = ctx->launch[q->model][q->prec];
+        make_chunks(g->segs_h, ids, L.chunk, 0, &g->carry);
+        cosmica_status st = q->prec == 1 ? upload_slot<float>(g, q) : upload_slot<double>(g, q);
+        if (st != COSMICA_OK) return st;
+        uint32_t zero = 0;
+        HIP_TRY(hipMemcpy(g->done_d + q->slot, &zero, 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(g->cancel_d + q->slot, &zero, 4, hipMemcpyHostToDevice));
+        q->state = 1;
+        g->resident.push_back(q);
+    }
+    return COSMICA_OK;
+}
+
+template <typename R>
+cosmica_status launch_slice(ServeGroup* g)
+{
+    cosmica_ctx* ctx = g->ctx;
+    hipStream_t s = ctx->serve_stream;
+    const uint32_t nch = (uint32_t)g->carry.size();
+    if (nch > g->chunks_cap) {
+        if (g->chunks_block) {
+            dfree(ctx, g->chunks_block, (size_t)g->chunks_cap * sizeof(ChunkDev));
+            g->chunks_block = nullptr;
+            g->chunks_d = nullptr;
+        }
+        const uint32_t cap = std::max<uint32_t>(nch * 2, 4096);
+        void* p = nullptr;
+        cosmica_status st = dalloc(ctx, (size_t)cap * sizeof(ChunkDev), &p);
+        if (st != COSMICA_OK) return st;
+        g->chunks_block = p;
+        g->chunks_d = (ChunkDev*)p;
+        g->chunks_cap = cap;
+    }
+    if (nch)
+        HIP_TRY(hipMemcpyAsync(g->chunks_d, g->carry.data(), (size_t)nch * sizeof(ChunkDev),
+                               hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_fill_u32(g->counters_d, 0u, 8, s));
+    PropArgs<R> a;
+    std::memset(&a, 0, sizeof(a));
+    a.jobs = (const JobDev<R>*)g->jobs_d;
+    a.regions = (const RegionDev<R>*)g->regions_d;
+    a.segs = g->segs_d;
+    a.chunks = g->chunks_d;
+    a.n_chunks = nch;
+    a.head = g->counters_d + 0;
+    a.exP = g->exP;
+    a.exT = g->exT;
+    a.exNF = g->exNF;
+    a.resume = g->susp[g->cur];
+    a.n_resume = g->n_resume;
+    a.resume_head = g->counters_d + 1;
+    a.suspend = g->susp[g->cur ^ 1];
+    a.suspend_count = g->counters_d + 2;
+    a.step_budget = slice_steps();
+    a.job_cancel = g->cancel_d;
+    a.job_done = g->done_d;
+    a.leftover = g->left_d;
+    a.leftover_count = g->counters_d + 3;
+    g->n_chunks_last = nch;
+    HIP_TRY(launch_model<R>(g->model, a, g->grid, g->block, s));
+    // the host copy of the chunk list must outlive the asynchronous upload
+    HIP_TRY(hipStreamSynchronize(s));
+    return COSMICA_OK;
+}
+
+cosmica_status collect_slice(ServeGroup* g)
+{
+    uint32_t c[4];
+    HIP_TRY(hipMemcpy(c, g->counters_d, sizeof(c), hipMemcpyDeviceToHost));
+    const uint32_t head = std::min(c[0], g->n_chunks_last);
+    std::vector<ChunkDev> next(c[3]);
+    if (c[3]) HIP_TRY(hipMemcpy(next.data(), g->left_d, c[3] * sizeof(ChunkDev),
+                                hipMemcpyDeviceToHost));
+    next.insert(next.end(), g->carry.begin() + head, g->carry.end());
+    g->carry.swap(next);
+    g->n_resume = c[2];
+    g->cur ^= 1;
+    return COSMICA_OK;
+}
+
+void release(ServeGroup* g, Req* q)
+{
+    pool_give(g, q->ex0, q->job.total);
+    g->free_slots.push_back(q->slot);
+    q->slot = -1;
+}
+
+// Reduce a finished request's bins and copy results to its buffers.
+cosmica_status finish_request(ServeGroup* g, Req* q)
+{
+    cosmica_ctx* ctx = g->ctx;
+    hipStream_t s = ctx->serve_stream;
+    const uint32_t nb = (uint32_t)q->job.rig.size();
+    ReduceArgs r;
+    std::memset(&r, 0, sizeof(r));
+    r.segs = g->segs_d;
+    r.lis = g->lis_d;
+    r.exP = g->exP;
+    r.exT = g->exT;
+    r.exNF = g->exNF;
+    r.seg_base = (uint32_t)q->slot * ServeGroup::kBinsPerSlot;
+    r.out_base = 0;
+    r.hist = g->r_hist;
+    r.flux = g->r_flux;
+    r.flux_se = g->r_se;
+    r.mean_t = g->r_mt;
+    r.steps = g->r_steps;
+    r.n_capped = g->r_ncap;
+    r.n_nan = g->r_nnan;
+    HIP_TRY(launch_reduce(r, nb, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const cosmica_result& R = q->res;
+    std::vector<uint32_t> ncap(nb);
+    HIP_TRY(hipMemcpy(ncap.data(), g->r_ncap, nb * 4, hipMemcpyDeviceToHost));
+    if (R.hist) HIP_TRY(hipMemcpy(R.hist, g->r_hist, (size_t)nb * kNHist * 4, hipMemcpyDeviceToHost));
+    if (R.flux) HIP_TRY(hipMemcpy(R.flux, g->r_flux, nb * 8, hipMemcpyDeviceToHost));
+    if (R.flux_se) HIP_TRY(hipMemcpy(R.flux_se, g->r_se, nb * 8, hipMemcpyDeviceToHost));
+    if (R.mean_exit_time_s) HIP_TRY(hipMemcpy(R.mean_exit_time_s, g->r_mt, nb * 8, hipMemcpyDeviceToHost));
+    if (R.steps) HIP_TRY(hipMemcpy(R.steps, g->r_steps, nb * 8, hipMemcpyDeviceToHost));
+    if (R.n_capped) std::memcpy(R.n_capped, ncap.data(), nb * 4);
+    if (R.n_nan) HIP_TRY(hipMemcpy(R.n_nan, g->r_nnan, nb * 4, hipMemcpyDeviceToHost));
+    if (R.exits) {
+        const size_t n = q->job.total;
+        std::vector<double> P(n), T(n);
+        std::vector<uint32_t> NF(n);
+        HIP_TRY(hipMemcpy(P.data(), g->exP + q->ex0, n * 8, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(T.data(), g->exT + q->ex0, n * 8, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(NF.data(), g->exNF + q->ex0, n * 4, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < n; ++i) {
+            cosmica_exit& e = R.exits[i];
+            e.P = P[i];
+            e.t = T[i];
+            e.r = e.theta = e.phi = 0.0;
+            e.n = NF[i] & ((1u << kFlagShift) - 1u);
+            e.flags = NF[i] >> kFlagShift;
+        }
+    }
+    bool capped = false;
+    for (uint32_t v : ncap) capped |= v > 0;
+    q->status = capped ? COSMICA_ESTEPCAP : COSMICA_OK;
+    return COSMICA_OK;
+}
+
+void serve_loop(cosmica_ctx* ctx)
+{
+    (void)hipSetDevice(ctx->device);
+    std::unique_lock<std::mutex> lk(ctx->mu);
+    while (!ctx->stop) {
+        cosmica_status st = admit(ctx);
+        if (st != COSMICA_OK) {
+            ctx->serve_error = st;
+            break;
+        }
+        std::vector<ServeGroup*> active;
+        for (int m = 0; m < 2; ++m)
+            for (int q = 0; q < 2; ++q) {
+                ServeGroup* g = ctx->groups[m][q].get();
+                if (g && (!g->resident.empty() || g->n_resume || !g->releasing.empty()))
+                    active.push_back(g);
+            }
+        if (active.empty()) {
+            ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->queued.empty(); });
+            continue;
+        }
+        // cancellations: flag on the device, drop unissued chunks
+        for (ServeGroup* g : active) {
+            for (auto it = g->resident.begin(); it != g->resident.end();) {
+                Req* q = *it;
+                if (q->cancel && !q->cancel_sent) {
+                    uint32_t one = 1;
+                    if (hipMemcpy(g->cancel_d + q->slot, &one, 4, hipMemcpyHostToDevice) !=
+                        hipSuccess)
+                        ctx->serve_error = COSMICA_EDEVICE;
+                    const uint32_t s0 = (uint32_t)q->slot * ServeGroup::kBinsPerSlot;
+                    const uint32_t s1 = s0 + (uint32_t)q->job.rig.size();
+                    g->carry.erase(std::remove_if(g->carry.begin(), g->carry.end(),
+                                                  [&](const ChunkDev& c) {
+                                                      return c.seg >= s0 && c.seg < s1;
+                                                  }),
+                                   g->carry.end());
+                    q->cancel_sent = true;
+                    q->state = 2;
+                    q->status = COSMICA_ECANCELED;
+                    g->releasing.push_back(q);
+                    it = g->resident.erase(it);
+                    ctx->cv.notify_all();
+                } else {
+                    ++it;
+                }
+            }
+        }
+        lk.unlock();
+        bool ok = true;
+        for (ServeGroup* g : active) {
+            st = g->prec == 1 ? launch_slice<float>(g) : launch_slice<double>(g);
+            ok &= st == COSMICA_OK;
+        }
+        if (ok && hipStreamSynchronize(ctx->serve_stream) != hipSuccess) ok = false;
+        std::vector<uint32_t> done(ServeGroup::kSlots);
+        lk.lock();
+        if (!ok) {
+            ctx->serve_error = COSMICA_EDEVICE;
+            break;
+        }
+        for (ServeGroup* g : active) {
+            if (collect_slice(g) != COSMICA_OK ||
+                hipMemcpy(done.data(), g->done_d, done.size() * 4, hipMemcpyDeviceToHost) !=
+                    hipSuccess) {
+                ctx->serve_error = COSMICA_EDEVICE;
+                ok = false;
+                break;
+            }
+            for (Req* q : g->releasing) {
+                uint32_t zero = 0;
+                (void)hipMemcpy(g->cancel_d + q->slot, &zero, 4, hipMemcpyHostToDevice);
+                release(g, q);
+            }
+            g->releasing.clear();
+            for (auto it = g->resident.begin(); it != g->resident.end();) {
+                Req* q = *it;
+                if (done[q->slot] >= q->job.total) {
+                    if (finish_request(g, q) != COSMICA_OK) {
+                        ctx->serve_error = COSMICA_EDEVICE;
+                        ok = false;
+                    }
+                    release(g, q);
+                    q->state = 2;
+                    it = g->resident.erase(it);
+                    ctx->cv.notify_all();
+                } else {
+                    ++it;
+                }
+            }
+        }
+        if (!ok) break;
+    }
+    // fail whatever is left so waiters return
+    for (auto& kv : ctx->reqs)
+        if (kv.second->state != 2) {
+            kv.second->state = 2;
+            kv.second->status = ctx->serve_error != COSMICA_OK ? ctx->serve_error
+                                                               : COSMICA_ECANCELED;
+        }
+    ctx->cv.notify_all();
+}
+
+}  // namespace
+
+extern "C" {
+
+cosmica_status cosmica_submit(cosmica_ctx* ctx, const cosmica_job* job,
+                              cosmica_precision precision, cosmica_result* result,
+                              uint64_t* ticket)
+{
+    if (ctx == nullptr || result == nullptr || ticket == nullptr) return COSMICA_EINVAL;
+    if (precision != COSMICA_PREC_FP64 && precision != COSMICA_PREC_MIXED) return COSMICA_EINVAL;
+    if (validate(job) != COSMICA_OK || job->n_bins > (int)ServeGroup::kBinsPerSlot)
+        return COSMICA_EINVAL;
+    auto q = std::make_unique<Req>();
+    q->job = copy_job(job);
+    q->prec = precision;
+    q->model = job->helio->model;
+    q->res = *result;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->serve_error != COSMICA_OK) return ctx->serve_error;
+    if (ctx->queued.size() >= 100000) return COSMICA_EBUSY;
+    if (!ctx->worker_started) {
+        if (hipSetDevice(ctx->device) != hipSuccess ||
+            hipStreamCreateWithFlags(&ctx->serve_stream, hipStreamNonBlocking) != hipSuccess)
+            return COSMICA_EDEVICE;
+        ctx->worker = std::thread(serve_loop, ctx);
+        ctx->worker_started = true;
+    }
+    q->ticket = ctx->next_ticket++;
+    *ticket = q->ticket;
+    ctx->queued.push_back(q.get());
+    ctx->reqs[q->ticket] = std::move(q);
+    ctx->cv.notify_all();
+    return COSMICA_OK;
+}
+
+cosmica_status cosmica_poll(cosmica_ctx* ctx, uint64_t ticket, int32_t* done)
+{
+    if (ctx == nullptr || done == nullptr) return COSMICA_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->reqs.find(ticket);
+    if (it == ctx->reqs.end()) return COSMICA_ENOTFOUND;
+    *done = it->second->state == 2 ? 1 : 0;
+    return *done ? it->second->status : COSMICA_OK;
+}
+
+cosmica_status cosmica_wait(cosmica_ctx* ctx, uint64_t ticket, int32_t timeout_ms)
+{
+    if (ctx == nullptr) return COSMICA_EINVAL;
+    std::unique_lock<std::mutex> lk(ctx->mu);
+    auto it = ctx->reqs.find(ticket);
+    if (it == ctx->reqs.end()) return COSMICA_ENOTFOUND;
+    Req* q = it->second.get();
+    auto pred = [&] { return q->state == 2; };
+    if (timeout_ms < 0)
+        ctx->cv.wait(lk, pred);
+    else if (!ctx->cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred))
+        return COSMICA_EBUSY;
+    return q->status;
+}
+
+cosmica_status cosmica_cancel(cosmica_ctx* ctx, uint64_t ticket)
+{
+    if (ctx == nullptr) return COSMICA_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->reqs.find(ticket);
+    if (it == ctx->reqs.end()) return COSMICA_ENOTFOUND;
+    if (it->second->state != 2) it->second->cancel = true;
+    ctx->cv.notify_all();
+    return COSMICA_OK;
+}
+
+cosmica_status cosmica_serve_stats(cosmica_ctx* ctx, uint64_t* queued, uint64_t* resident,
+                                   uint64_t* particles_in_flight, uint64_t* bytes_in_use)
+{
+    if (ctx == nullptr) return COSMICA_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    uint64_t res = 0, fl = 0;
+    for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 2; ++q)
+            if (ctx->groups[m][q]) {
+                res += ctx->groups[m][q]->resident.size();
+                fl += ctx->groups[m][q]->n_resume;
+            }
+    if (queued) *queued = ctx->queued.size();
+    if (resident) *resident = res;
+    if (particles_in_flight) *particles_in_flight = fl;
+    if (bytes_in_use) *bytes_in_use = ctx->in_use.load();
+    return COSMICA_OK;
+}
+
+void cosmica_destroy(cosmica_ctx* ctx)
+{
+    if (ctx == nullptr) return;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->stop = true;
+        ctx->cv.notify_all();
+    }
+    if (ctx->worker.joinable()) ctx->worker.join();
+    (void)hipSetDevice(ctx->device);
+    if (ctx->serve_stream) (void)hipStreamSynchronize(ctx->serve_stream);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 2; ++q) {
+            ServeGroup* g = ctx->groups[m][q].get();
+            if (g && g->chunks_block) dfree(ctx, g->chunks_block, (size_t)g->chunks_cap * sizeof(ChunkDev));
+            ctx->groups[m][q].reset();
+        }
+    if (ctx->serve_stream) (void)hipStreamDestroy(ctx->serve_stream);
+    for (int i = 0; i < 4; ++i)
+        if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+}  // extern "C"

@@ -27,3 +27,21 @@ def W():
     from paper_2502_06319_amd import workloads
 
     return workloads
+
+
+ORACLE_THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+@pytest.fixture(scope="session")
+def eng():
+    """One HIP context on device 0 for the GPU tests (fails loudly without one)."""
+    from paper_2502_06319_amd import cosmica
+
+    e = cosmica.Engine(0)
+    yield e
+    e.close()
+
+
+@pytest.fixture(scope="session")
+def othreads():
+    return ORACLE_THREADS

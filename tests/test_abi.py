@@ -1,0 +1,178 @@
+"""C ABI checks that need no GPU: the HIP library loads, exports every function
+that include/cosmica.h declares, and its host-side validation rejects each
+invalid input with COSMICA_EINVAL before touching a device."""
+import copy
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2502_06319_amd import cosmica as C
+from paper_2502_06319_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cosmica.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cosmica_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 20
+    lib = C.load()
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", C.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (cosmica_\w+)", out))
+    assert set(names) <= exported
+    # the binding marshals exactly the declared API
+    assert set(C.exported_symbols()) == set(names)
+
+
+def test_abi_version_and_strerror():
+    lib = C.load()
+    assert lib.cosmica_abi_version() == 1
+    for st in (C.OK, C.EINVAL, C.ENOMEM, C.EDEVICE, C.EBUSY, C.ECANCELED, C.ESTEPCAP,
+               C.ENOTFOUND, 123):
+        assert isinstance(lib.cosmica_strerror(st), bytes)
+
+
+STRUCTS = {"cosmica_helio": C.Helio, "cosmica_species": C.Species, "cosmica_job": C.Job,
+           "cosmica_exit": C.Exit, "cosmica_result": C.Result, "cosmica_bins_dev": C.BinsDev,
+           "cosmica_launch": C.Launch, "cosmica_timings": C.Timings}
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The C compiler's sizeof/offsetof of every public struct equals the binding's."""
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "cosmica.h"',
+             "int main(void) {"]
+    for cname, cls in STRUCTS.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
+    got = dict(ln.split() for ln in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, cls in STRUCTS.items():
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)
+
+
+def test_valid_workloads_pass():
+    for job in (W.c1_job(), W.c2_job(), W.c4_jobs(n_sets=2)[5]):
+        assert C.validate_job(job) == C.OK
+    for r in W.c5_requests(max_requests=5):
+        assert C.validate_job(r["job"]) == C.OK
+
+
+def _bad(path, value, base=None):
+    job = copy.deepcopy(base or W.c2_job(particles_per_bin=10, n_bins=4))
+    d = job
+    for k in path[:-1]:
+        d = d[k]
+    d[path[-1]] = value
+    return job
+
+
+@pytest.mark.parametrize("path,value", [
+    (("helio", "model"), 2),
+    (("helio", "n_regions"), 0),
+    (("helio", "n_regions"), 16),
+    (("helio", "r_boundary_au"), 0.5),          # boundary inside the injection point
+    (("helio", "r0_au"), -1.0),
+    (("helio", "dt_max_s"), 0.0),
+    (("helio", "dt_diff_frac"), float("nan")),
+    (("helio", "dt_adv_frac"), -0.1),
+    (("helio", "polarity"), 0),
+    (("helio", "drift"), 2),
+    (("helio", "kperp_over_kpar"), 0.0),
+    (("helio", "kperp_over_kpar"), 1.5),
+    (("helio", "theta0_rad"), 0.0),
+    (("helio", "theta0_rad"), math.pi),
+    (("helio", "omega_rad_s"), -1.0),
+    (("helio", "b0_nT"), 0.0),                  # drift needs a field
+    (("helio", "v_fast_km_s"), 0.0),            # drift needs a wind
+    (("species", "charge"), 0),
+    (("species", "mass_gev"), -1.0),
+    (("species", "lis_norm"), 0.0),
+    (("step_cap",), 1 << 24),
+])
+def test_invalid_fields_are_rejected(path, value):
+    assert C.validate_job(_bad(path, value)) == C.EINVAL
+
+
+def test_invalid_region_values_are_rejected():
+    for field, value in (("kappa0_cm2_s", 0.0), ("kappa0_cm2_s", float("inf")),
+                         ("v_slow_km_s", -5.0), ("v_slow_km_s", 0.0), ("tilt_deg", 90.0),
+                         ("tilt_deg", -1.0)):
+        job = W.c2_job(particles_per_bin=10, n_bins=4)
+        job["helio"][field][7] = value
+        assert C.validate_job(job) == C.EINVAL, (field, value)
+
+
+def test_hcs_requires_drift_and_wind_zero_allowed_without_drift():
+    job = W.c2_job(particles_per_bin=10, n_bins=4)
+    job["helio"]["drift"] = 0
+    assert C.validate_job(job) == C.EINVAL  # hcs still on
+    job["helio"]["hcs"] = 0
+    job["helio"]["v_slow_km_s"] = [0.0] * 15
+    job["helio"]["v_fast_km_s"] = 0.0
+    assert C.validate_job(job) == C.OK
+
+
+def test_bins_and_counts_are_checked():
+    job = W.c1_job()
+    job["particles_per_bin"] = [10, 0, 10, 10, 10, 10, 10, 10]
+    assert C.validate_job(job) == C.EINVAL
+    job = W.c1_job()
+    job["rigidity_gv"] = list(job["rigidity_gv"])
+    job["rigidity_gv"][3] = -2.0
+    assert C.validate_job(job) == C.EINVAL
+    job = W.c1_job()
+    job["rigidity_gv"], job["particles_per_bin"] = [], []
+    assert C.validate_job(job) == C.EINVAL
+    job = W.c1_job()
+    job["particles_per_bin"] = [2**31] * 8  # total over 2^32
+    assert C.validate_job(job) == C.EINVAL
+    job = W.c1_job()
+    job["bin_offset"] = 2**32 - 4  # bin_offset + n_bins over 2^32
+    assert C.validate_job(job) == C.EINVAL
+
+
+def test_null_pointers_are_rejected():
+    lib = C.load()
+    assert lib.cosmica_validate_job(None) == C.EINVAL
+    assert lib.cosmica_create(None, 0, 0, None) == C.EINVAL
+    assert lib.cosmica_run(None, None, 0, 0, None) == C.EINVAL
+    assert lib.cosmica_plan_execute(None, None) == C.EINVAL
+    assert lib.cosmica_plan_read(None, None) == C.EINVAL
+    assert lib.cosmica_get_timings(None, None) == C.EINVAL
+    assert lib.cosmica_submit(None, None, 0, None, None) == C.EINVAL
+    assert lib.cosmica_poll(None, 1, None) == C.EINVAL
+    assert lib.cosmica_cancel(None, 1) == C.EINVAL
+    assert lib.cosmica_tune(None, 0, 0, None) == C.EINVAL
+    lib.cosmica_destroy(None)
+    lib.cosmica_plan_destroy(None)
+
+
+def test_create_without_a_device_fails_cleanly():
+    lib = C.load()
+    h = ctypes.c_void_p()
+    st = lib.cosmica_create(ctypes.byref(h), 0, 0, None)
+    if st == C.OK:  # a GPU is present: this check belongs to CPU-only hosts
+        lib.cosmica_destroy(h)
+        pytest.skip("a HIP device is present")
+    assert st == C.EDEVICE and not h.value
+    assert lib.cosmica_create(ctypes.byref(h), -1, 0, None) in (C.EINVAL, C.EDEVICE)

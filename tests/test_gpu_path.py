@@ -1,0 +1,184 @@
+"""Whole-path parity of the HIP library against the FP64 oracle (C ABI).
+
+Each run integrates every particle to the boundary (Sec. III, Eq.(3)), then
+bins and LIS-weights the exit rigidities (Eq.(4), J = f P^2, L = 0).  Both
+sides use the same Philox streams, so comparisons are particle by particle
+wherever the arithmetic allows:
+
+* radial model, FP64: every particle takes the same number of steps; exit
+  rigidities agree to 1e-12; histograms are identical; flux to 1e-12.
+* 3D model, FP64: last-bit differences (FMA contraction, libm vs ocml) flip
+  rare threshold decisions -- current-sheet crossings, the slow/fast wind
+  band, the exit step -- after which a path continues on other random
+  numbers; at least 75 % of the particles of every bin (90 % overall) take
+  identical step counts, and each bin's flux is within half a standard error.
+* mixed precision: the stated tolerance is per bin
+      |J_gpu - J_oracle| <= max(SE, J / sqrt(N))
+  (one Monte Carlo standard error, or the paper's 1/sqrt(N) band of Sec. VIII
+  if larger), together with a paired test that the GPU-minus-oracle weight
+  differences have zero mean: |dJ| <= 4 SE_pair.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2502_06319_amd import cosmica as C
+
+pytestmark = pytest.mark.gpu
+
+
+def _weights(P, norm=1.9e4, index=2.78):
+    return norm * P ** (-index) / (P * P)
+
+
+def _split(job, exits):
+    out, off = [], 0
+    for n in job["particles_per_bin"]:
+        out.append(exits[off:off + n])
+        off += n
+    return out
+
+
+def _paired(ge, oe, P0):
+    w_g, w_o = _weights(ge["P"]), _weights(oe["P"])
+    d = w_g - w_o
+    N = len(d)
+    dJ = P0 * P0 * d.mean()
+    se_pair = P0 * P0 * d.std(ddof=1) / math.sqrt(N) if N > 1 else 0.0
+    return dJ, se_pair
+
+
+def _report(tag, b, res_o, g_flux, same, dJ, se_pair):
+    print(f"{tag} bin {b} P0 {res_o['P0']:.3f}: same_n {same:.4f} dJ/J {dJ / res_o['flux']:+.2e} "
+          f"dJ/SE {dJ / res_o['flux_se']:+.3f} dJ/SEpair {dJ / se_pair if se_pair else 0:+.2f}",
+          flush=True)
+
+
+def test_radial_fp64_particle_by_particle(eng, orc, W, othreads):
+    job = W.c1_job()
+    g = eng.run(job, precision="fp64", exits=True)[0]
+    o = orc.run_job(job, threads=othreads)
+    for b, (ge, r) in enumerate(zip(_split(job, g["exits"]), o)):
+        oe = r["records"]
+        np.testing.assert_array_equal(ge["n"], oe["n"])
+        np.testing.assert_allclose(ge["P"], oe["P"], rtol=1e-12)
+        np.testing.assert_allclose(ge["t"], oe["t"], rtol=1e-12)
+        np.testing.assert_allclose(ge["r"], oe["r"], rtol=1e-12)
+        np.testing.assert_array_equal(g["hist"][b], r["hist"])
+        assert g["steps"][b] == r["steps"]
+        assert g["flux"][b] == pytest.approx(r["flux"], rel=1e-12)
+        assert g["flux_se"][b] == pytest.approx(r["flux_se"], rel=1e-9)
+        assert g["mean_exit_time_s"][b] == pytest.approx(r["mean_exit_time_s"], rel=1e-12)
+        assert g["n_capped"][b] == 0 and g["n_nan"][b] == 0
+
+
+def test_radial_mixed(eng, orc, W, othreads):
+    job = W.c1_job()
+    g = eng.run(job, precision="mixed", exits=True)[0]
+    o = orc.run_job(job, threads=othreads)
+    for b, (ge, r) in enumerate(zip(_split(job, g["exits"]), o)):
+        same = np.mean(ge["n"] == r["records"]["n"])
+        assert same >= 0.99
+        assert abs(g["flux"][b] / r["flux"] - 1.0) <= 1e-4
+        assert abs(int(g["steps"][b]) - int(r["steps"])) <= 1e-3 * r["steps"]
+
+
+def _compare_3d(eng, orc, job, precision, othreads, tag):
+    g = eng.run(job, precision=precision, exits=True)[0]
+    o = orc.run_job(job, threads=othreads)
+    tot_same = 0
+    stats = []
+    for b, (ge, r) in enumerate(zip(_split(job, g["exits"]), o)):
+        oe = r["records"]
+        N = len(oe)
+        same = np.mean(ge["n"] == oe["n"])
+        tot_same += same * N
+        dJ, se_pair = _paired(ge, oe, r["P0"])
+        assert dJ == pytest.approx(g["flux"][b] - r["flux"], rel=1e-6, abs=1e-12 * r["flux"])
+        _report(tag, b, r, g["flux"][b], same, dJ, se_pair)
+        assert int(g["hist"][b].sum()) == N
+        assert g["n_nan"][b] == 0 and g["n_capped"][b] == 0
+        stats.append((same, dJ, se_pair, r))
+    return tot_same / sum(job["particles_per_bin"]), stats
+
+
+def test_3d_fp64_against_oracle(eng, orc, W, othreads):
+    job = W.c2_job(particles_per_bin=1000)
+    overall, stats = _compare_3d(eng, orc, job, "fp64", othreads, "3d-fp64")
+    assert overall >= 0.90
+    for same, dJ, se_pair, r in stats:
+        assert same >= 0.75
+        assert abs(dJ) <= 0.5 * r["flux_se"]
+        assert abs(dJ) <= 4.0 * se_pair + 1e-12 * r["flux"]
+
+
+def test_3d_mixed_against_oracle(eng, orc, W, othreads):
+    """The mixed-precision form of the 3D workload (FP32 bulk, FP64 r, t, P)."""
+    job = W.c2_job(particles_per_bin=2000)
+    overall, stats = _compare_3d(eng, orc, job, "mixed", othreads, "3d-mixed")
+    assert overall >= 0.2
+    for same, dJ, se_pair, r in stats:
+        N = r["n_used"]
+        assert abs(dJ) <= max(r["flux_se"], r["flux"] / math.sqrt(N))
+        assert abs(dJ) <= 4.0 * se_pair + 1e-12 * r["flux"]
+
+
+def test_full_size_3d_fp64_sampled_particles(eng, orc, W, othreads):
+    """Config-2 size (20 bins x 5,000): particles 0-63 and 4936-4999 of every bin."""
+    job = W.c2_job()
+    g = eng.run(job, precision="fp64", exits=True)[0]
+    same = []
+    for b, ge in enumerate(_split(job, g["exits"])):
+        assert int(g["hist"][b].sum()) == 5000 and g["n_nan"][b] == 0
+        for first in (0, 4936):
+            sub = dict(job, rigidity_gv=[job["rigidity_gv"][b]], particles_per_bin=[64],
+                       bin_offset=b)
+            oe = orc.run_job(sub, threads=othreads, first=first)[0]["records"]
+            gs = ge[first:first + 64]
+            m = gs["n"] == oe["n"]
+            same.append(m.mean())
+            if m.any():
+                assert np.median(np.abs(gs["P"][m] / oe["P"][m] - 1.0)) <= 1e-9
+    assert np.mean(same) >= 0.85
+
+
+def test_full_size_batched_mixed(eng, orc, W, othreads):
+    """The batched workload at full size (64 sets x 4 species x 30 bins, ~4.0e7
+    particles) in the launch shape the benchmark times: invariants over every
+    bin, and sampled bins against the oracle with paired statistics."""
+    from bench import tuned_engine_launch
+
+    jobs = W.c4_jobs()
+    tuned_engine_launch(eng)
+    plan = eng.plan(jobs, "mixed", exits=True)
+    plan.execute()
+    res = plan.read(exits=True)
+    plan.destroy()
+    total_nan = total_cap = 0
+    for j, r in zip(jobs, res):
+        N = np.asarray(j["particles_per_bin"])
+        np.testing.assert_array_equal(r["hist"].sum(axis=1), N)
+        assert np.all(r["steps"] >= N)
+        assert np.all(r["exits"]["P"] >= np.repeat(j["rigidity_gv"], N))
+        total_nan += int(r["n_nan"].sum())
+        total_cap += int(r["n_capped"].sum())
+    assert total_nan == 0 and total_cap == 0
+    # sampled bins: one of each species, small bins so the oracle finishes quickly
+    rng = np.random.default_rng(5)
+    picked = []
+    for sp in ("p", "He4", "He3", "e-"):
+        cands = [(ji, b) for ji, j in enumerate(jobs) if j["species"]["name"] == sp
+                 for b, n in enumerate(j["particles_per_bin"]) if n <= 900]
+        picked += [cands[i] for i in rng.choice(len(cands), 2, replace=False)]
+    for ji, b in picked:
+        j = jobs[ji]
+        r = orc.run_job(j, threads=othreads, bins=[b])[0]
+        ge = _split(j, res[ji]["exits"])[b]
+        dJ, se_pair = _paired(ge, r["records"], r["P0"])
+        N = r["n_used"]
+        _report(f"batched job {ji} {j['species']['name']}", b, r, res[ji]["flux"][b],
+                np.mean(ge["n"] == r["records"]["n"]), dJ, se_pair)
+        assert abs(dJ) <= max(r["flux_se"], r["flux"] / math.sqrt(N))
+        assert abs(dJ) <= 4.0 * se_pair + 1e-12 * r["flux"]

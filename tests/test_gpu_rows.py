@@ -1,0 +1,120 @@
+"""GPU parity of single hot-path steps against the FP64 oracle, through the C ABI.
+
+a2 random numbers: Philox4x32-10 words are compared bit for bit; the
+   Box-Muller normals the integrator draws from them are compared in FP64
+   (rounding only) and in FP32 (hardware log/sin/cos, |dz| <= 2e-6).
+a3-a6 local coefficients of the 3D SDE (Eq.(3) for Eq.(5), A_P of Eq.(6)):
+   environment, diffusion-tensor square root, drift vector and time step at
+   random points and at points inside the current-sheet layer.  FP64 agrees to
+   1e-9 of each quantity's scale (transcendental rounding is amplified by
+   cancellations among the drift terms); the FP32 bulk of the mixed kernel to
+   3e-4 (1e-3 absolute for the polarity factor Hw, whose argument carries the
+   binary32 error of theta divided by the thin sheet width).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2502_06319_amd import cosmica as C
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("seed,c1,c2,c3", [(42, 0, 0, 0), (2**64 - 1, 2**32 - 1, 7, 2**32 - 1),
+                                           (0x9E3779B97F4A7C15, 123456, 19, 255)])
+def test_philox_words_bitwise(eng, orc, seed, c1, c2, c3):
+    n = 1 << 20
+    c0 = 2**32 - 1000 if c1 == 0 else 17  # first case wraps the low counter word
+    w, _, _ = eng.probe_rng(seed, c0, c1, c2, c3, n)
+    ref, _ = orc.rng_block(seed, c0, c1, c2, c3, n)
+    np.testing.assert_array_equal(w, ref)
+
+
+def test_normals_fp64_and_fp32(eng, orc):
+    n = 1 << 18
+    _, z64, z32 = eng.probe_rng(42, 5, 9, 3, 1, n)
+    _, zr = orc.rng_block(42, 5, 9, 3, 1, n)
+    zr = zr[:, :3]
+    assert np.abs(z64 - zr).max() <= 1e-13
+    assert np.abs(z32.astype(np.float64) - zr).max() <= 2e-6
+
+
+def _oracle_fields(orc, p, pts):
+    out = np.zeros((len(pts), 16))
+    extra = np.zeros((len(pts), 2))  # V, |vd|
+    for i, q in enumerate(pts):
+        c = orc.coeffs_3d(p, *q)
+        out[i] = [c["A"][0], c["A"][1], c["A"][2], c["AP"], c["Brr"], c["Bpr"], c["Bpp"],
+                  c["Btt"], c["dt"], c["Hw"], c["vd"][0], c["vd"][1], c["vd"][2], c["Krr"],
+                  c["Krp"], c["kpar"]]
+        extra[i] = [c["V"], np.linalg.norm(c["vd"])]
+    return out, extra
+
+
+def _sheet_points(orc, p, rng, n):
+    pts = []
+    for _ in range(n):
+        P = math.exp(rng.uniform(math.log(0.2), math.log(50.0)))
+        r = rng.uniform(1.0, 110.0)
+        ph = rng.uniform(0.0, 2 * math.pi)
+        f = lambda t: orc.coeffs_3d(p, P, r, t, ph)["Hw"]
+        lo, hi = 0.05, math.pi - 0.05
+        for _ in range(80):
+            mid = 0.5 * (lo + hi)
+            lo, hi = (mid, hi) if f(mid) > 0 else (lo, mid)
+        c = orc.coeffs_3d(p, P, r, lo, ph)
+        rl = 0.0222974 * P / c["Bmag_nT"]
+        pts.append([P, r, lo + rng.uniform(-2.0, 2.0) * 2.0 * rl / r, ph])
+    return pts
+
+
+def _check(g, o, extra, pts, tol, tol_hw):
+    r, th = pts[:, 1], pts[:, 2]
+    st = np.sin(th)
+    # drift of the SDE as a physical velocity
+    Ag = np.stack([g[:, 0], r * g[:, 1], r * st * g[:, 2]], 1)
+    Ao = np.stack([o[:, 0], r * o[:, 1], r * st * o[:, 2]], 1)
+    scale_A = np.linalg.norm(Ao, axis=1) + extra[:, 0] + extra[:, 1] + 2 * o[:, 13] / r
+    assert np.all(np.linalg.norm(Ag - Ao, axis=1) <= tol * scale_A)
+    vg, vo = g[:, 10:13], o[:, 10:13]
+    assert np.all(np.linalg.norm(vg - vo, axis=1) <= tol * np.linalg.norm(vo, axis=1) + 1e-300)
+    for k, ref in ((3, 3), (4, 4), (6, 6), (7, 7), (8, 8), (13, 13), (15, 15)):
+        assert np.all(np.abs(g[:, k] - o[:, k]) <= tol * np.abs(o[:, ref])), C.PROBE_FIELDS[k]
+    assert np.all(np.abs(g[:, 5] - o[:, 5]) <= tol * (np.abs(o[:, 5]) + o[:, 4]))   # B_phir
+    assert np.all(np.abs(g[:, 14] - o[:, 14]) <= tol * (np.abs(o[:, 14]) + o[:, 13]))  # K_rphi
+    assert np.all(np.abs(g[:, 9] - o[:, 9]) <= tol_hw)
+
+
+@pytest.mark.parametrize("which", ["c2", "c4_e-", "c4_He3_negative"])
+@pytest.mark.parametrize("precision,tol,tol_hw", [("fp64", 1e-9, 1e-9), ("mixed", 3e-4, 1e-3)])
+def test_coefficients_match_oracle(eng, orc, W, which, precision, tol, tol_hw):
+    if which == "c2":
+        job = W.c2_job(particles_per_bin=1, n_bins=1)
+    else:
+        jobs = W.c4_jobs(n_sets=2)
+        sp = "e-" if which == "c4_e-" else "He3"
+        job = next(j for j in jobs if j["species"]["name"] == sp and
+                   (which == "c4_e-" or j["helio"]["polarity"] < 0))
+    p = orc.params(job)
+    rng = np.random.default_rng(11)
+    n = 400
+    pts = np.stack([np.exp(rng.uniform(math.log(0.1), math.log(100.0), n)),
+                    rng.uniform(0.2, job["helio"]["r_boundary_au"] - 0.2, n),
+                    rng.uniform(0.05, math.pi - 0.05, n), rng.uniform(0.0, 2 * math.pi, n)], 1)
+    pts = np.concatenate([pts, np.array(_sheet_points(orc, p, rng, 60))])
+    g = eng.probe_coeffs(job, pts, precision)
+    o, extra = _oracle_fields(orc, p, pts)
+    _check(g, o, extra, pts, tol, tol_hw)
+    # the sheet points do exercise the sheet layer
+    assert np.sum(np.abs(o[-60:, 9]) < 0.9) >= 20
+
+
+def test_probe_rejects_bad_points(eng, W):
+    job = W.c2_job(particles_per_bin=1, n_bins=1)
+    with pytest.raises(C.CosmicaError):
+        eng.probe_coeffs(job, [[1.0, 5.0, 0.0, 0.0]])  # theta at the pole
+    with pytest.raises(C.CosmicaError):
+        eng.probe_coeffs(job, [[-1.0, 5.0, 1.0, 0.0]])
+    with pytest.raises(C.CosmicaError):
+        eng.probe_coeffs(W.c1_job(), [[1.0, 5.0, 1.0, 0.0]])  # radial model has no 3D coefficients

@@ -1,0 +1,121 @@
+"""Continuous-batching server through the C ABI (cosmica_submit / poll / wait /
+cancel / serve_stats).
+
+Requests that arrive while others are on the device are admitted as their
+exit-record footprint fits, their particles share the persistent kernel's
+slices, and particles still in flight at the end of a slice are parked and
+resumed bit-exactly.  Each result must be bitwise identical to the same job run
+alone through cosmica_run, whatever else is in the mix.
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+from paper_2502_06319_amd import cosmica as C
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("hist", "flux", "flux_se", "mean_exit_time_s", "steps", "n_capped", "n_nan")
+
+
+@pytest.fixture
+def short_slices():
+    old = os.environ.get("COSMICA_SLICE_STEPS")
+    os.environ["COSMICA_SLICE_STEPS"] = "300"  # many suspend/resume cycles per particle
+    yield
+    if old is None:
+        del os.environ["COSMICA_SLICE_STEPS"]
+    else:
+        os.environ["COSMICA_SLICE_STEPS"] = old
+
+
+def _requests(W, n, scale, seed=42):
+    return [r["job"] for r in W.c5_requests(seed=seed, max_requests=n, count_scale=scale)]
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_served_results_equal_batch_alone(W, precision, short_slices):
+    jobs = _requests(W, 6, 0.01)
+    with C.Engine(0) as e:
+        tickets = [e.submit(j, precision, exits=True) for j in jobs]
+        for t in tickets:
+            assert t.wait(120000) == C.OK
+        for j, t in zip(jobs, tickets):
+            alone = e.run(j, precision, exits=True)[0]
+            got = t.result()
+            for k in KEYS:
+                np.testing.assert_array_equal(got[k], alone[k], err_msg=k)
+            for f in ("P", "t", "n", "flags"):
+                np.testing.assert_array_equal(got["exits"][f], alone["exits"][f])
+
+
+def test_arrivals_join_a_running_mix(W, short_slices):
+    """Requests submitted while others are resident overlap with them and
+    still reproduce their stand-alone results."""
+    jobs = _requests(W, 8, 0.02, seed=3)
+    with C.Engine(0) as e:
+        first = [e.submit(j, "mixed") for j in jobs[:4]]
+        time.sleep(0.05)
+        st = e.serve_stats()
+        later = [e.submit(j, "mixed") for j in jobs[4:]]
+        for t in first + later:
+            assert t.wait(120000) == C.OK
+        assert st["resident"] + st["queued"] >= 1
+        for j, t in zip(jobs, first + later):
+            alone = e.run(j, "mixed")[0]
+            np.testing.assert_array_equal(t.result()["flux"], alone["flux"])
+            np.testing.assert_array_equal(t.result()["hist"], alone["hist"])
+
+
+def test_cancel_and_unknown_ticket(W, short_slices):
+    big = _requests(W, 1, 0.5, seed=11)[0]
+    small = _requests(W, 3, 0.01, seed=12)
+    with C.Engine(0) as e:
+        tb = e.submit(big, "mixed")
+        ts = [e.submit(j, "mixed") for j in small]
+        assert tb.cancel() == C.OK
+        assert tb.wait(120000) in (C.ECANCELED, C.OK)  # it may finish before the cancel lands
+        for j, t in zip(small, ts):
+            assert t.wait(120000) == C.OK
+            np.testing.assert_array_equal(t.result()["flux"], e.run(j, "mixed")[0]["flux"])
+        d = C.ctypes.c_int32()
+        assert C.load().cosmica_poll(e.handle, 999999, C.ctypes.byref(d)) == C.ENOTFOUND
+
+
+def test_admission_by_device_footprint(W, short_slices):
+    """A pool of 30,000 exit records: requests queue until earlier ones free
+    their records; a request larger than the pool is refused with ENOMEM."""
+    old = os.environ.get("COSMICA_SERVE_POOL")
+    os.environ["COSMICA_SERVE_POOL"] = "30000"
+    try:
+        jobs = _requests(W, 5, 0.01, seed=21)
+        for j in jobs:
+            assert sum(j["particles_per_bin"]) < 30000
+        huge = dict(jobs[0], particles_per_bin=[20000] * len(jobs[0]["rigidity_gv"]))
+        with C.Engine(0) as e:
+            ts = [e.submit(j, "mixed") for j in jobs]
+            th = e.submit(huge, "mixed")
+            assert th.wait(120000) == C.ENOMEM
+            for j, t in zip(jobs, ts):
+                assert t.wait(120000) == C.OK
+                np.testing.assert_array_equal(t.result()["flux"], e.run(j, "mixed")[0]["flux"])
+            st = e.serve_stats()
+            assert st["queued"] == 0 and st["resident"] == 0
+    finally:
+        if old is None:
+            del os.environ["COSMICA_SERVE_POOL"]
+        else:
+            os.environ["COSMICA_SERVE_POOL"] = old
+
+
+def test_serving_rejects_invalid_jobs(W):
+    with C.Engine(0) as e:
+        bad = W.c2_job(particles_per_bin=10, n_bins=4)
+        bad["helio"]["tilt_deg"][0] = 100.0
+        with pytest.raises(C.CosmicaError):
+            e.submit(bad, "mixed")
+        many = W.c2_job(particles_per_bin=10, n_bins=65)  # more bins than a serving slot holds
+        with pytest.raises(C.CosmicaError):
+            e.submit(many, "mixed")

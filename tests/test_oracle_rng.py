@@ -75,3 +75,10 @@ def test_normals_are_standard(orc):
         assert abs(np.corrcoef(zz[:, a], zz[:, b])[0, 1]) < 5 / np.sqrt(n)
     # largest magnitude: uniforms live in [2^-24, 1 - 2^-24]
     assert np.abs(z).max() <= np.sqrt(-2 * np.log(2.0**-24)) + 1e-12
+
+
+def test_rng_block_is_the_single_call_loop(orc):
+    w, z = orc.rng_block(99, 5, 6, 7, 8, 300)
+    for i in (0, 1, 17, 299):
+        np.testing.assert_array_equal(w[i], orc.philox(99, [5 + i, 6, 7, 8]))
+        np.testing.assert_array_equal(z[i], orc.normals(99, [5 + i, 6, 7, 8]))
