@@ -47,20 +47,24 @@ OPS_PER_STEP = {
     "1d": {"philox4x32_10": 80, "uniforms": 8, "box_muller": 5, "region": 3,
            "beta_kappa": 7, "coefficients": 12, "time_step": 5, "em_update": 13},
 }
-# Peak VALU lane-operation rates: 256 CUs x 2.4 GHz x 128 FP32 lanes/clk
-# (157.3 TFLOP/s / 2 flops per FMA) and x 64 FP64 lanes/clk (78.6 TFLOP/s / 2).
-PEAK_TOPS = {"mixed": 78.6, "fp64": 39.3}
+# Peak VALU lane-operation issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz =
+# 39.3 T lane-ops/s, for FP32 without packed math (the published 157.3 TFLOP/s
+# counts packed FP32 FMA as 4 flops) and for full-rate FP64 (78.6 TFLOP/s / 2).
+PEAK_TOPS = {"mixed": 39.3, "fp64": 39.3}
+TUNE_SAMPLE = {"mixed": 4_000_000, "fp64": 1_000_000}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def tuned_engine_launch(eng: C.Engine) -> dict:
-    """Launch shapes picked by the tuner (cached per device architecture)."""
+def tuned_engine_launch(eng: C.Engine, jobs=None) -> dict:
+    """Launch shapes the tuner picked on a down-scaled copy of the batched
+    workload (cached per device architecture, model and precision)."""
+    jobs = W.c4_jobs() if jobs is None else jobs
     out = {}
     for prec in ("mixed", "fp64"):
-        out[prec] = eng.tune(C.MODEL_3D, prec, TUNE_CACHE)
+        out[prec] = eng.tune_jobs(jobs, prec, TUNE_SAMPLE[prec], TUNE_CACHE)
     return out
 
 
@@ -150,14 +154,14 @@ def serve(eng, seconds, rate, precision, seed=42):
     }
 
 
-def cpu_baseline(seconds_target=12.0):
+def cpu_baseline(seconds_target=15.0):
     """The FP64 oracle on a bounded, seeded sample of the batched workload."""
     from oracle import oracle as O
 
     threads = max(1, min(16, os.cpu_count() or 1))
     jobs = W.c4_jobs()
     rng = np.random.default_rng(7)
-    picks = [(int(rng.integers(len(jobs))), int(rng.integers(30))) for _ in range(64)]
+    picks = [(int(rng.integers(len(jobs))), int(rng.integers(30))) for _ in range(4096)]
     per = 96
     steps = 0
     t0 = time.perf_counter()
@@ -185,7 +189,13 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="time the batched pass only (profiling runs)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
+    if args.batched_only:
+        args.no_plain = args.no_serve = args.no_cpu = True
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the quasi-particles are "
               "independent and a multi-GPU run would shard whole bins; see the design notes.",
@@ -195,11 +205,19 @@ def main():
     import torch  # device synchronisation around the timed region
 
     sync = torch.cuda.synchronize
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib << 18  # float32 elements
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        sync()
+        log(f"copy calibration: {args.copy_calibration_mib} MiB read + written")
+        del src, dst
     eng = C.Engine(0)
-    launch = tuned_engine_launch(eng)
+    jobs = W.c4_jobs()
+    launch = tuned_engine_launch(eng, jobs)
     log("launch shapes:", launch)
 
-    jobs = W.c4_jobs()
     n_particles = W.total_particles(jobs)
     plan = eng.plan(jobs, "mixed")
     log(f"batched workload: {len(jobs)} spectra, {n_particles} particles")

@@ -123,6 +123,8 @@ _SIGS = {
                                           ctypes.POINTER(Launch)]),
     "cosmica_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_char_p]),
+    "cosmica_tune_jobs": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Job), ctypes.c_int32,
+                                         ctypes.c_int, ctypes.c_uint64, ctypes.c_char_p]),
     "cosmica_get_timings": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Timings)]),
     "cosmica_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Job), ctypes.c_int,
                                       ctypes.POINTER(Result), c_u64_p]),
@@ -366,6 +368,17 @@ class Engine:
         p = cache_path.encode() if cache_path else None
         _check(load().cosmica_tune(self.handle, model, PRECISION[precision], p), "tune")
         return self.get_launch(model, precision)
+
+    def tune_jobs(self, jobs, precision, sample_particles: int,
+                  cache_path: str | None = None) -> dict:
+        """Tune on a down-scaled copy of the given jobs (all of one model)."""
+        jobs = [jobs] if isinstance(jobs, dict) else list(jobs)
+        packs = [_JobPack(j) for j in jobs]
+        jarr = (Job * len(packs))(*[p.job for p in packs])
+        p = cache_path.encode() if cache_path else None
+        _check(load().cosmica_tune_jobs(self.handle, jarr, len(packs), PRECISION[precision],
+                                        int(sample_particles), p), "tune_jobs")
+        return self.get_launch(int(jobs[0]["helio"]["model"]), precision)
 
     def timings(self) -> dict:
         t = Timings()

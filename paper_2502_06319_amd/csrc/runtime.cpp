@@ -988,65 +988,132 @@ void cache_store(const char* path, const std::string& key, const cosmica_launch&
 
 }  // namespace
 
+namespace {
+
+// Steps/s of one launch shape on a calibration batch (second of two runs).
+cosmica_status time_shape(cosmica_ctx* ctx, const cosmica_job* jobs, int n_jobs, int model,
+                          int precision, const cosmica_launch& c, double* rate)
+{
+    ctx->launch[model][precision] = c;
+    cosmica_plan* p = nullptr;
+    cosmica_status st = cosmica_plan_create(ctx, jobs, n_jobs, (cosmica_precision)precision, 0, &p);
+    if (st != COSMICA_OK) return st;
+    *rate = 0.0;
+    for (int rep = 0; rep < 2 && st == COSMICA_OK; ++rep) {
+        st = cosmica_plan_execute(p, nullptr);
+        cosmica_timings t;
+        if (st == COSMICA_OK) st = cosmica_get_timings(ctx, &t);
+        if (st == COSMICA_OK && rep == 1 && t.propagate_ms > 0.0)
+            *rate = (double)t.steps / (t.propagate_ms * 1e-3);
+    }
+    cosmica_plan_destroy(p);
+    return st;
+}
+
+// Coordinate sweep: workgroup size, then resident workgroups per CU, then the
+// refill chunk, then the queue order, each from the best shape so far.
+cosmica_status sweep(cosmica_ctx* ctx, const cosmica_job* jobs, int n_jobs, int model,
+                     int precision, const char* cache_path)
+{
+    const std::string key = tune_key(ctx, model, precision);
+    const cosmica_launch saved = ctx->launch[model][precision];
+    cosmica_launch best{256, 0, 256, 0};
+    double best_rate = -1.0;
+    auto consider = [&](const cosmica_launch& c) -> cosmica_status {
+        if (!launch_ok(c)) return COSMICA_OK;
+        double rate = 0.0;
+        cosmica_status st = time_shape(ctx, jobs, n_jobs, model, precision, c, &rate);
+        if (st != COSMICA_OK) return st;
+        if (rate > best_rate) {
+            best_rate = rate;
+            best = c;
+        }
+        return COSMICA_OK;
+    };
+    cosmica_status st = COSMICA_OK;
+    for (int blk : {256, 128, 64})
+        if ((st = consider(cosmica_launch{blk, 0, best.chunk, best.order})) != COSMICA_OK) break;
+    if (st == COSMICA_OK) {
+        int occ = 0;
+        if (occupancy_propagate(model, precision, best.block, &occ) != hipSuccess || occ < 1) occ = 1;
+        const cosmica_launch base = best;
+        for (int bpc : {occ - occ / 4, occ / 2})
+            if (bpc >= 1 && bpc < occ &&
+                (st = consider(cosmica_launch{base.block, bpc, base.chunk, base.order})) != COSMICA_OK)
+                break;
+    }
+    if (st == COSMICA_OK) {
+        const cosmica_launch base = best;
+        for (int ch : {16, 64, 1024})
+            if ((st = consider(cosmica_launch{base.block, base.blocks_per_cu, ch, base.order})) !=
+                COSMICA_OK)
+                break;
+    }
+    if (st == COSMICA_OK) {
+        const cosmica_launch base = best;
+        st = consider(cosmica_launch{base.block, base.blocks_per_cu, base.chunk, 1 - base.order});
+    }
+    if (st != COSMICA_OK) {
+        ctx->launch[model][precision] = saved;
+        return st;
+    }
+    ctx->launch[model][precision] = best;
+    cache_store(cache_path, key, best, best_rate);
+    return COSMICA_OK;
+}
+
+}  // namespace
+
 extern "C" cosmica_status cosmica_tune(cosmica_ctx* ctx, cosmica_model model,
                                        cosmica_precision precision, const char* cache_path)
 {
     if (ctx == nullptr || (model != 0 && model != 1) || (precision != 0 && precision != 1))
         return COSMICA_EINVAL;
-    const std::string key = tune_key(ctx, model, precision);
     cosmica_launch L;
-    if (cache_lookup(cache_path, key, &L)) {
+    if (cache_lookup(cache_path, tune_key(ctx, model, precision), &L)) {
         ctx->launch[model][precision] = L;
         return COSMICA_OK;
     }
     HIP_TRY(hipSetDevice(ctx->device));
-    // about four resident waves' worth of particles per SIMD at the default shape
+    // about two resident waves' worth of particles per SIMD at full occupancy
     const uint64_t lanes = (uint64_t)ctx->num_cus * 4 * 64 * 8;
     Calib cal;
     make_calibration(model, (uint32_t)std::max<uint64_t>(64, 2 * lanes / 16), &cal);
-    const int blocks[] = {64, 128, 256};
-    const int chunks[] = {64, 256, 1024};
-    cosmica_launch best = ctx->launch[model][precision];
-    double best_rate = -1.0;
-    const cosmica_launch saved = ctx->launch[model][precision];
-    for (int blk : blocks) {
-        int occ = 0;
-        if (occupancy_propagate(model, precision, blk, &occ) != hipSuccess || occ < 1) continue;
-        std::vector<int> bpcs = {0};
-        if (occ >= 2) bpcs.push_back(std::max(1, occ / 2));
-        for (int bpc : bpcs) {
-            for (int ch : chunks) {
-                cosmica_launch c{blk, bpc, ch, 1};
-                ctx->launch[model][precision] = c;
-                cosmica_plan* p = nullptr;
-                cosmica_status st = cosmica_plan_create(ctx, &cal.job, 1, precision, 0, &p);
-                if (st != COSMICA_OK) {
-                    ctx->launch[model][precision] = saved;
-                    return st;
-                }
-                double rate = 0.0;
-                for (int rep = 0; rep < 2 && st == COSMICA_OK; ++rep) {
-                    st = cosmica_plan_execute(p, nullptr);
-                    cosmica_timings t;
-                    if (st == COSMICA_OK) st = cosmica_get_timings(ctx, &t);
-                    if (st == COSMICA_OK && rep == 1 && t.propagate_ms > 0.0)
-                        rate = (double)t.steps / (t.propagate_ms * 1e-3);
-                }
-                cosmica_plan_destroy(p);
-                if (st != COSMICA_OK) {
-                    ctx->launch[model][precision] = saved;
-                    return st;
-                }
-                if (rate > best_rate) {
-                    best_rate = rate;
-                    best = c;
-                }
-            }
-        }
+    return sweep(ctx, &cal.job, 1, model, precision, cache_path);
+}
+
+extern "C" cosmica_status cosmica_tune_jobs(cosmica_ctx* ctx, const cosmica_job* jobs,
+                                            int32_t n_jobs, cosmica_precision precision,
+                                            uint64_t sample_particles, const char* cache_path)
+{
+    if (ctx == nullptr || jobs == nullptr || n_jobs < 1 || sample_particles < 1 ||
+        (precision != 0 && precision != 1))
+        return COSMICA_EINVAL;
+    uint64_t total = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        if (validate(&jobs[j]) != COSMICA_OK) return COSMICA_EINVAL;
+        if (jobs[j].helio->model != jobs[0].helio->model) return COSMICA_EINVAL;
+        for (int b = 0; b < jobs[j].n_bins; ++b) total += jobs[j].particles_per_bin[b];
     }
-    ctx->launch[model][precision] = best;
-    cache_store(cache_path, key, best, best_rate);
-    return COSMICA_OK;
+    const int model = jobs[0].helio->model;
+    cosmica_launch L;
+    if (cache_lookup(cache_path, tune_key(ctx, model, precision), &L)) {
+        ctx->launch[model][precision] = L;
+        return COSMICA_OK;
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    // the same jobs with every bin's count scaled to the sample size (>= 1 each)
+    const double f = std::min(1.0, (double)sample_particles / (double)total);
+    std::vector<std::vector<uint32_t>> counts(n_jobs);
+    std::vector<cosmica_job> sample(jobs, jobs + n_jobs);
+    for (int j = 0; j < n_jobs; ++j) {
+        counts[j].resize(jobs[j].n_bins);
+        for (int b = 0; b < jobs[j].n_bins; ++b)
+            counts[j][b] = std::max<uint32_t>(
+                1, (uint32_t)std::llround(f * (double)jobs[j].particles_per_bin[b]));
+        sample[j].particles_per_bin = counts[j].data();
+    }
+    return sweep(ctx, sample.data(), n_jobs, model, precision, cache_path);
 }
 
 // ---------------------------------------------------------------------------

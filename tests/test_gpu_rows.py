@@ -65,7 +65,8 @@ def _sheet_points(orc, p, rng, n):
             lo, hi = (mid, hi) if f(mid) > 0 else (lo, mid)
         c = orc.coeffs_3d(p, P, r, lo, ph)
         rl = 0.0222974 * P / c["Bmag_nT"]
-        pts.append([P, r, lo + rng.uniform(-2.0, 2.0) * 2.0 * rl / r, ph])
+        th = lo + rng.uniform(-2.0, 2.0) * 2.0 * rl / r
+        pts.append([P, r, min(max(th, 0.05), math.pi - 0.05), ph])
     return pts
 
 

@@ -113,37 +113,69 @@ def test_step_cap(eng, orc, W, othreads):
     assert int(sum(g["n_capped"])) == int(np.sum(ex["flags"] == 1)) > 0
 
 
-def test_plan_repeats_and_writes_torch_buffers(eng, W):
-    torch = pytest.importorskip("torch")
+def test_plan_repeats(eng, W):
     jobs = [W.c2_job(particles_per_bin=500, n_bins=5), W.c1_job(particles_per_bin=200)]
     jobs[1]["job_tag"] = 9
     plan = eng.plan(jobs, "mixed")
-    info = plan.info()
-    assert info == {"bins": 13, "particles": 5 * 500 + 8 * 200, "jobs": 2}
+    assert plan.info() == {"bins": 13, "particles": 5 * 500 + 8 * 200, "jobs": 2}
     plan.execute()
     a = plan.read()
     plan.execute()
     b = plan.read()
     for x, y in zip(a, b):
         assert_same(x, y, exits=False)
-    nb = info["bins"]
-    dev = torch.device("cuda:0")
-    out = {"hist": torch.zeros((nb, C.NHIST), dtype=torch.int32, device=dev),
-           "flux": torch.zeros(nb, dtype=torch.float64, device=dev),
-           "flux_se": torch.zeros(nb, dtype=torch.float64, device=dev),
-           "mean_exit_time_s": torch.zeros(nb, dtype=torch.float64, device=dev),
-           "steps": torch.zeros(nb, dtype=torch.int64, device=dev),
-           "n_capped": torch.zeros(nb, dtype=torch.int32, device=dev),
-           "n_nan": torch.zeros(nb, dtype=torch.int32, device=dev)}
-    torch.cuda.synchronize()
-    plan.execute(out)
-    eng.timings()  # waits for the plan's stream
-    torch.cuda.synchronize()
-    flux = out["flux"].cpu().numpy()
-    np.testing.assert_array_equal(flux, np.concatenate([a[0]["flux"], a[1]["flux"]]))
-    np.testing.assert_array_equal(out["hist"].cpu().numpy().astype(np.uint32),
-                                  np.concatenate([a[0]["hist"], a[1]["hist"]]))
     plan.destroy()
+
+
+TORCH_CHILD = r"""
+import sys, numpy as np
+import torch                                   # first: one HIP runtime for both
+sys.path.insert(0, sys.argv[1])
+from paper_2502_06319_amd import cosmica as C, workloads as W
+jobs = [W.c2_job(particles_per_bin=500, n_bins=5), W.c1_job(particles_per_bin=200)]
+jobs[1]["job_tag"] = 9
+stream = torch.cuda.Stream()
+eng = C.Engine(0, stream=stream)               # runs on torch's stream
+plan = eng.plan(jobs, "mixed")
+plan.execute()
+a = plan.read()
+nb = 13
+dev = torch.device("cuda:0")
+out = {"hist": torch.zeros((nb, C.NHIST), dtype=torch.int32, device=dev),
+       "flux": torch.zeros(nb, dtype=torch.float64, device=dev),
+       "flux_se": torch.zeros(nb, dtype=torch.float64, device=dev),
+       "mean_exit_time_s": torch.zeros(nb, dtype=torch.float64, device=dev),
+       "steps": torch.zeros(nb, dtype=torch.int64, device=dev),
+       "n_capped": torch.zeros(nb, dtype=torch.int32, device=dev),
+       "n_nan": torch.zeros(nb, dtype=torch.int32, device=dev)}
+torch.cuda.synchronize()
+plan.execute(out)
+stream.synchronize()
+np.testing.assert_array_equal(out["flux"].cpu().numpy(), np.concatenate([a[0]["flux"], a[1]["flux"]]))
+np.testing.assert_array_equal(out["hist"].cpu().numpy().astype(np.uint32),
+                              np.concatenate([a[0]["hist"], a[1]["hist"]]))
+np.testing.assert_array_equal(out["steps"].cpu().numpy().astype(np.uint64),
+                              np.concatenate([a[0]["steps"], a[1]["steps"]]))
+plan.destroy()
+eng.close()
+print("torch-ok")
+"""
+
+
+def test_torch_stream_and_device_buffers():
+    """torch as plumbing: the context runs on a torch stream and a plan writes
+    its per-bin results straight into torch device tensors.  Run in a fresh
+    process that imports torch first, so that torch and the library share the
+    one HIP runtime torch ships with."""
+    import subprocess
+    import sys
+
+    pytest.importorskip("torch")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", TORCH_CHILD, root], capture_output=True,
+                         text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert "torch-ok" in out.stdout
 
 
 def test_timings_count_every_step(eng, W):
