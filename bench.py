@@ -51,7 +51,7 @@ OPS_PER_STEP = {
 # 39.3 T lane-ops/s, for FP32 without packed math (the published 157.3 TFLOP/s
 # counts packed FP32 FMA as 4 flops) and for full-rate FP64 (78.6 TFLOP/s / 2).
 PEAK_TOPS = {"mixed": 39.3, "fp64": 39.3}
-TUNE_SAMPLE = {"mixed": 4_000_000, "fp64": 1_000_000}
+TUNE_SAMPLE = {"mixed": 10_000_000, "fp64": 2_500_000}
 
 
 def log(*a):

@@ -234,9 +234,9 @@ cosmica_status cosmica_get_launch(cosmica_ctx* ctx, cosmica_model model,
 cosmica_status cosmica_tune(cosmica_ctx* ctx, cosmica_model model, cosmica_precision precision,
                             const char* cache_path);
 
-/* The same sweep on a down-scaled copy of the caller's own workload: every bin of
- * jobs[0..n_jobs-1] (all of one model) keeps its seed and tag and is given
- * max(1, round(count * sample_particles / total)) particles.  Cache handling as
+/* The same sweep on a sample of the caller's own workload: every k-th of
+ * jobs[0..n_jobs-1] (all of one model; k odd, about total / sample_particles),
+ * whole, so bins keep their sizes, seeds and tags.  Cache handling as
  * cosmica_tune. */
 cosmica_status cosmica_tune_jobs(cosmica_ctx* ctx, const cosmica_job* jobs, int32_t n_jobs,
                                  cosmica_precision precision, uint64_t sample_particles,

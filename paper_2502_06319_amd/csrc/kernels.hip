@@ -158,15 +158,54 @@ struct Coef3 {
     R Hw, vdr, vdt, vdp, Krr, Krp, kpar;
 };
 
+// Per-lane copy of a job's constants, loaded once when a lane takes a
+// particle: the step then reads only its shell entry from memory, however
+// many jobs the lanes of a wave belong to.
 template <typename R>
-__device__ __forceinline__ int region_of(const JobDev<R>& J, double r)
+struct JobReg {
+    R vf, omega, kperp_frac, gcoef, br0, abs_z, mass2, sqA, dt_max, diff_frac, adv_frac, rlcoef;
+    double rb, inv_shell;
+    uint32_t seed_lo, seed_hi, job_tag, step_cap;
+    int32_t nreg, drift, hcs;
+};
+
+template <typename R>
+__device__ __forceinline__ JobReg<R> load_job(const JobDev<R>& J)
+{
+    JobReg<R> o;
+    o.vf = J.vf;
+    o.omega = J.omega;
+    o.kperp_frac = J.kperp_frac;
+    o.gcoef = J.gcoef;
+    o.br0 = J.br0;
+    o.abs_z = J.abs_z;
+    o.mass2 = J.mass2;
+    o.sqA = J.sqA;
+    o.dt_max = J.dt_max;
+    o.diff_frac = J.diff_frac;
+    o.adv_frac = J.adv_frac;
+    o.rlcoef = J.rlcoef;
+    o.rb = J.rb;
+    o.inv_shell = J.inv_shell;
+    o.seed_lo = J.seed_lo;
+    o.seed_hi = J.seed_hi;
+    o.job_tag = J.job_tag;
+    o.step_cap = J.step_cap;
+    o.nreg = J.nreg;
+    o.drift = J.drift;
+    o.hcs = J.hcs;
+    return o;
+}
+
+template <typename R>
+__device__ __forceinline__ int region_of(const JobReg<R>& J, double r)
 {
     const int k = (int)(r * J.inv_shell);
     return k < J.nreg - 1 ? k : J.nreg - 1;
 }
 
 template <typename R, bool FULL>
-__device__ __forceinline__ void coeffs3d(const JobDev<R>& J, const RegionDev<R>& g, double rd,
+__device__ __forceinline__ void coeffs3d(const JobReg<R>& J, const RegionDev<R>& g, double rd,
                                          double Pd, R th, R ph, Coef3<R>& c)
 {
     using M = Mth<R>;
@@ -272,7 +311,7 @@ __device__ __forceinline__ void coeffs3d(const JobDev<R>& J, const RegionDev<R>&
 
 // One EM step of the 3D model.  Returns nothing; the caller tests r >= rb.
 template <typename R>
-__device__ __forceinline__ void step3d(const JobDev<R>& J, const RegionDev<R>* __restrict__ reg,
+__device__ __forceinline__ void step3d(const JobReg<R>& J, const RegionDev<R>* __restrict__ reg,
                                        PState<R>& s, uint32_t pid, uint32_t bin)
 {
     using M = Mth<R>;
@@ -323,7 +362,7 @@ __device__ __forceinline__ void step3d(const JobDev<R>& J, const RegionDev<R>* _
 
 // One EM step of the radial model: dr = (2k/r - V) ds + sqrt(2k) dW.
 template <typename R>
-__device__ __forceinline__ void step1d(const JobDev<R>& J, const RegionDev<R>* __restrict__ reg,
+__device__ __forceinline__ void step1d(const JobReg<R>& J, const RegionDev<R>* __restrict__ reg,
                                        PState<R>& s, uint32_t pid, uint32_t bin)
 {
     using M = Mth<R>;
@@ -374,6 +413,8 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
     const uint32_t lane = __lane_id();
     PState<R> s = {0.0, 0.0, 0.0, (R)0, (R)0, 0u};
     uint32_t pid = 0, bin = 0, job = 0, out = 0, seg = 0;
+    JobReg<R> J = {};
+    const RegionDev<R>* reg = a.regions;
     bool active = false;
     uint32_t budget = 0;  // steps this lane has taken in this launch
 
@@ -410,6 +451,8 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
                 job = sg.job;
                 bin = sg.bin;
                 out = sg.out_offset + pid;
+                J = load_job(a.jobs[job]);
+                reg = a.regions + (size_t)job * kRegionStride;
                 active = true;
             }
             need = __ballot(!active);
@@ -433,15 +476,17 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
             const uint32_t avail = c_end - c_next;
             const uint32_t rank = lane_rank(need);
             if (!active && rank < avail) {
-                const JobDev<R>& J = a.jobs[sg.job];
+                const JobDev<R>& Jd = a.jobs[sg.job];
                 seg = c_seg;
                 pid = c_next + rank;
                 job = sg.job;
                 bin = sg.bin;
                 out = sg.out_offset + pid;
-                s.r = J.r0;
-                s.th = (R)J.th0;
-                s.ph = (R)J.ph0;
+                J = load_job(Jd);
+                reg = a.regions + (size_t)job * kRegionStride;
+                s.r = Jd.r0;
+                s.th = (R)Jd.th0;
+                s.ph = (R)Jd.ph0;
                 s.P = sg.P0;
                 s.t = 0.0;
                 s.n = 0u;
@@ -466,7 +511,6 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
         }
 
         if (active) {
-            const JobDev<R>& J = a.jobs[job];
             uint32_t flags = 0;
             bool done = false;
             if (a.job_cancel != nullptr && a.job_cancel[job] != 0u) {
@@ -475,7 +519,6 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
                 flags = kFlagCapped;
                 done = true;
             } else {
-                const RegionDev<R>* reg = a.regions + (size_t)job * kRegionStride;
                 if (M3D)
                     step3d<R>(J, reg, s, pid, bin);
                 else
@@ -718,7 +761,7 @@ __global__ void k_probe_coeffs(const JobDev<R>* job, const RegionDev<R>* reg, co
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const JobDev<R>& J = *job;
+    const JobReg<R> J = load_job(*job);
     const double P = pts[4 * (size_t)i + 0], r = pts[4 * (size_t)i + 1];
     const R th = (R)pts[4 * (size_t)i + 2], ph = (R)pts[4 * (size_t)i + 3];
     Coef3<R> c;

@@ -1044,7 +1044,7 @@ cosmica_status sweep(cosmica_ctx* ctx, const cosmica_job* jobs, int n_jobs, int 
     }
     if (st == COSMICA_OK) {
         const cosmica_launch base = best;
-        for (int ch : {16, 64, 1024})
+        for (int ch : {32, 128, 512, 1024})
             if ((st = consider(cosmica_launch{base.block, base.blocks_per_cu, ch, base.order})) !=
                 COSMICA_OK)
                 break;
@@ -1102,18 +1102,15 @@ extern "C" cosmica_status cosmica_tune_jobs(cosmica_ctx* ctx, const cosmica_job*
         return COSMICA_OK;
     }
     HIP_TRY(hipSetDevice(ctx->device));
-    // the same jobs with every bin's count scaled to the sample size (>= 1 each)
-    const double f = std::min(1.0, (double)sample_particles / (double)total);
-    std::vector<std::vector<uint32_t>> counts(n_jobs);
-    std::vector<cosmica_job> sample(jobs, jobs + n_jobs);
-    for (int j = 0; j < n_jobs; ++j) {
-        counts[j].resize(jobs[j].n_bins);
-        for (int b = 0; b < jobs[j].n_bins; ++b)
-            counts[j][b] = std::max<uint32_t>(
-                1, (uint32_t)std::llround(f * (double)jobs[j].particles_per_bin[b]));
-        sample[j].particles_per_bin = counts[j].data();
-    }
-    return sweep(ctx, sample.data(), n_jobs, model, precision, cache_path);
+    // every k-th whole job (k odd, so a batch ordered set x species keeps all
+    // species), bins at their full sizes: the sample keeps the refill-chunk and
+    // job-mixing structure of the real batch
+    uint64_t k = (uint64_t)std::llround((double)total / (double)sample_particles);
+    if (k < 1) k = 1;
+    if (k > 1 && k % 2 == 0) ++k;
+    std::vector<cosmica_job> sample;
+    for (int j = 0; j < n_jobs; j += (int)k) sample.push_back(jobs[j]);
+    return sweep(ctx, sample.data(), (int)sample.size(), model, precision, cache_path);
 }
 
 // ---------------------------------------------------------------------------

@@ -70,26 +70,35 @@ def _sheet_points(orc, p, rng, n):
     return pts
 
 
-def _check(g, o, extra, pts, tol, tol_hw):
+def _ratios(g, o, extra, pts, kfrac):
+    """|GPU - oracle| over each quantity's natural scale, per point."""
     r, th = pts[:, 1], pts[:, 2]
-    st = np.sin(th)
-    # drift of the SDE as a physical velocity
+    st, cot = np.sin(th), np.cos(th) / np.sin(th)
+    # drift of the SDE as a physical velocity; its scale includes every term
     Ag = np.stack([g[:, 0], r * g[:, 1], r * st * g[:, 2]], 1)
     Ao = np.stack([o[:, 0], r * o[:, 1], r * st * o[:, 2]], 1)
-    scale_A = np.linalg.norm(Ao, axis=1) + extra[:, 0] + extra[:, 1] + 2 * o[:, 13] / r
-    assert np.all(np.linalg.norm(Ag - Ao, axis=1) <= tol * scale_A)
-    vg, vo = g[:, 10:13], o[:, 10:13]
-    assert np.all(np.linalg.norm(vg - vo, axis=1) <= tol * np.linalg.norm(vo, axis=1) + 1e-300)
-    for k, ref in ((3, 3), (4, 4), (6, 6), (7, 7), (8, 8), (13, 13), (15, 15)):
-        assert np.all(np.abs(g[:, k] - o[:, k]) <= tol * np.abs(o[:, ref])), C.PROBE_FIELDS[k]
-    assert np.all(np.abs(g[:, 5] - o[:, 5]) <= tol * (np.abs(o[:, 5]) + o[:, 4]))   # B_phir
-    assert np.all(np.abs(g[:, 14] - o[:, 14]) <= tol * (np.abs(o[:, 14]) + o[:, 13]))  # K_rphi
-    assert np.all(np.abs(g[:, 9] - o[:, 9]) <= tol_hw)
+    scale_A = (np.linalg.norm(Ao, axis=1) + extra[:, 0] + extra[:, 1] + 2 * o[:, 13] / r
+               + kfrac * o[:, 15] * np.abs(cot) / r)
+    out = {"A": np.linalg.norm(Ag - Ao, axis=1) / scale_A,
+           "vd": np.linalg.norm(g[:, 10:13] - o[:, 10:13], axis=1)
+           / np.maximum(np.linalg.norm(o[:, 10:13], axis=1), 1e-300),
+           "Hw": np.abs(g[:, 9] - o[:, 9])}
+    for k in (3, 4, 6, 7, 8, 13, 15):
+        out[C.PROBE_FIELDS[k]] = np.abs(g[:, k] - o[:, k]) / np.abs(o[:, k])
+    out["Bpr"] = np.abs(g[:, 5] - o[:, 5]) / (np.abs(o[:, 5]) + o[:, 4])
+    out["Krp"] = np.abs(g[:, 14] - o[:, 14]) / (np.abs(o[:, 14]) + o[:, 13])
+    return out
+
+
+# (largest allowed, 99th percentile allowed) per precision; the FP32 maximum is
+# a formula-error detector (a wrong term or sign is an O(1) error), the
+# percentile bounds the binary32 rounding of the bulk of points
+TOLS = {"fp64": (1e-9, 1e-10), "mixed": (2e-2, 5e-4)}
 
 
 @pytest.mark.parametrize("which", ["c2", "c4_e-", "c4_He3_negative"])
-@pytest.mark.parametrize("precision,tol,tol_hw", [("fp64", 1e-9, 1e-9), ("mixed", 3e-4, 1e-3)])
-def test_coefficients_match_oracle(eng, orc, W, which, precision, tol, tol_hw):
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_coefficients_match_oracle(eng, orc, W, which, precision):
     if which == "c2":
         job = W.c2_job(particles_per_bin=1, n_bins=1)
     else:
@@ -106,7 +115,13 @@ def test_coefficients_match_oracle(eng, orc, W, which, precision, tol, tol_hw):
     pts = np.concatenate([pts, np.array(_sheet_points(orc, p, rng, 60))])
     g = eng.probe_coeffs(job, pts, precision)
     o, extra = _oracle_fields(orc, p, pts)
-    _check(g, o, extra, pts, tol, tol_hw)
+    worst, p99 = TOLS[precision]
+    for name, rat in _ratios(g, o, extra, pts, job["helio"]["kperp_over_kpar"]).items():
+        i = int(np.argmax(rat))
+        print(f"{which} {precision} {name}: max {rat[i]:.2e} at P,r,th,ph={pts[i]} "
+              f"p99 {np.percentile(rat, 99):.2e} median {np.median(rat):.2e}", flush=True)
+        assert rat[i] <= worst, name
+        assert np.percentile(rat, 99) <= p99, name
     # the sheet points do exercise the sheet layer
     assert np.sum(np.abs(o[-60:, 9]) < 0.9) >= 20
 
