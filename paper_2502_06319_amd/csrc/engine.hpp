@@ -30,13 +30,15 @@ struct alignas(16) JobDev {
     double r0, th0, ph0, pad1;
     R vf;          // fast wind [AU/s]
     R omega;       // solar rotation [rad/s]
-    R kperp_frac;  // kappa_perp / kappa_par
+    R kperp_frac;  // f = kappa_perp / kappa_par
+    R omf;         // 1 - f
+    R sqf2;        // 2 sqrt(f)
+    R twof;        // 2 f
     R gcoef;       // kappa_A / sqrt(1+G^2) = gcoef * beta * P * r^2 / (1+G^2)
-    R br0;         // radial field at 1 AU [nT]
+    R hb;          // 1/Delta = hb sqrt(1+G^2) / (r P): B_r(1 AU) / (2 x Larmor coefficient)
     R abs_z, mass2;
     R sqA;         // sign(Z) * polarity
     R dt_max, diff_frac, adv_frac;
-    R rlcoef;      // Larmor radius [AU] = rlcoef * P[GV] / |B|[nT]
 };
 
 // One radial shell: kappa0 [AU^2/s], slow wind [AU/s], tilt [rad], tan(tilt),
@@ -90,6 +92,8 @@ struct PropArgs {
     SuspendDev* suspend;
     uint32_t* suspend_count;      // zeroed before launch
     uint32_t step_budget;         // steps per lane per launch (0xffffffff: unlimited)
+    uint32_t uniform_key;         // 1: every job of the launch has the Philox key below
+    uint32_t key_lo, key_hi;
     const uint32_t* job_cancel;   // optional per-job cancel flags
     uint32_t* job_done;           // optional per-job count of finished particles
     ChunkDev* leftover;           // chunk remainders a wave held when its slice ended

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "engine.hpp"
 
@@ -63,17 +64,12 @@ struct Mth<float> {
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
-    static __device__ __forceinline__ float ln(float x)
-    {
-        return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
-    }
     // sin(2 pi x), cos(2 pi x)
     static __device__ __forceinline__ void sincos_rev(float x, float* s, float* c)
     {
         *s = __builtin_amdgcn_sinf(x);
         *c = __builtin_amdgcn_cosf(x);
     }
-    static __device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf(x); }
     static __device__ __forceinline__ void sincos_rad(float x, float* s, float* c)
     {
         sincos_rev(x * 0.159154943091895336f, s, c);
@@ -85,9 +81,10 @@ struct Mth<float> {
         const float e = __builtin_amdgcn_exp2f(-2.88539008177792681f * fabsf(x));
         return copysignf((1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e), x);
     }
+    // x - 2 pi floor(x / 2 pi): in [0, 2 pi) up to one rounding
     static __device__ __forceinline__ float fmod2pi(float x)
     {
-        return ::fmodf(x, (float)kTwoPi);
+        return x - (float)kTwoPi * floorf(x * 0.159154943091895336f);
     }
 };
 
@@ -98,12 +95,6 @@ struct Mth<double> {
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
     static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
     static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
-    static __device__ __forceinline__ double ln(double x) { return ::log(x); }
-    static __device__ __forceinline__ void sincos_rev(double x, double* s, double* c)
-    {
-        ::sincospi(2.0 * x, s, c);
-    }
-    static __device__ __forceinline__ double cos_rev(double x) { return ::cospi(2.0 * x); }
     static __device__ __forceinline__ void sincos_rad(double x, double* s, double* c)
     {
         ::sincos(x, s, c);
@@ -113,11 +104,16 @@ struct Mth<double> {
     static __device__ __forceinline__ double fmod2pi(double x) { return ::fmod(x, kTwoPi); }
 };
 
-template <typename R>
-__device__ __forceinline__ R uniform_of(uint32_t x)
+// Uniform in (0,1): (floor(x / 2^9) + 1/2) * 2^-23, exact in binary32 and
+// binary64.  In binary32 it is built from the bits: 1 + floor(x/2^9) 2^-23 has
+// the 23 bits as mantissa, and subtracting 1 - 2^-24 is exact.
+__device__ __forceinline__ float uniform_f32(uint32_t x)
 {
-    // (floor(x / 2^9) + 1/2) * 2^-23: exact in binary32 and binary64
-    return ((R)(x >> 9) + (R)0.5) * (R)1.1920928955078125e-07;
+    return __uint_as_float((x >> 9) | 0x3F800000u) - 0.99999994039535522f;
+}
+__device__ __forceinline__ double uniform_f64(uint32_t x)
+{
+    return ((double)(x >> 9) + 0.5) * 1.1920928955078125e-07;
 }
 
 // Box-Muller: z0, z1 from (u0, u1), z2 from (u2, u3).
@@ -126,16 +122,32 @@ __device__ __forceinline__ void normals(uint32_t k0, uint32_t k1, uint32_t n, ui
                                         uint32_t bin, uint32_t tag, R* z)
 {
     const uint4 x = philox4x32_10(k0, k1, n, pid, bin, tag);
-    const R rho0 = Mth<R>::sqrt((R)-2.0 * Mth<R>::ln(uniform_of<R>(x.x)));
-    if (NZ == 1) {
-        z[0] = rho0 * Mth<R>::cos_rev(uniform_of<R>(x.y));
+    if constexpr (std::is_same<R, float>::value) {
+        // sqrt(-2 ln u) = sqrt(log2(u) * (-2 ln 2))
+        const float rho0 = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(uniform_f32(x.x)) *
+                                                  -1.38629436111989061f);
+        if (NZ == 1) {
+            z[0] = rho0 * __builtin_amdgcn_cosf(uniform_f32(x.y));
+        } else {
+            const float u1 = uniform_f32(x.y);
+            const float rho2 = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(uniform_f32(x.z)) *
+                                                      -1.38629436111989061f);
+            z[0] = rho0 * __builtin_amdgcn_cosf(u1);
+            z[1] = rho0 * __builtin_amdgcn_sinf(u1);
+            z[2] = rho2 * __builtin_amdgcn_cosf(uniform_f32(x.w));
+        }
     } else {
-        R s1, c1;
-        Mth<R>::sincos_rev(uniform_of<R>(x.y), &s1, &c1);
-        const R rho2 = Mth<R>::sqrt((R)-2.0 * Mth<R>::ln(uniform_of<R>(x.z)));
-        z[0] = rho0 * c1;
-        z[1] = rho0 * s1;
-        z[2] = rho2 * Mth<R>::cos_rev(uniform_of<R>(x.w));
+        const double rho0 = ::sqrt(-2.0 * ::log(uniform_f64(x.x)));
+        if (NZ == 1) {
+            z[0] = rho0 * ::cospi(2.0 * uniform_f64(x.y));
+        } else {
+            double s1, c1;
+            ::sincospi(2.0 * uniform_f64(x.y), &s1, &c1);
+            const double rho2 = ::sqrt(-2.0 * ::log(uniform_f64(x.z)));
+            z[0] = rho0 * c1;
+            z[1] = rho0 * s1;
+            z[2] = rho2 * ::cospi(2.0 * uniform_f64(x.w));
+        }
     }
 }
 
@@ -155,6 +167,7 @@ struct Coef3 {
     R Ar, At, Ap, AP;      // drift of the SDE (r, theta, phi per unit time), dP/ds
     R Brr, Bpr, Bpp, Btt;  // B with B B^T = 2K
     R dt;
+    R invr, invst;         // 1/r, 1/sin(theta) of the step
     R Hw, vdr, vdt, vdp, Krr, Krp, kpar;
 };
 
@@ -163,7 +176,8 @@ struct Coef3 {
 // many jobs the lanes of a wave belong to.
 template <typename R>
 struct JobReg {
-    R vf, omega, kperp_frac, gcoef, br0, abs_z, mass2, sqA, dt_max, diff_frac, adv_frac, rlcoef;
+    R vf, omega, kfrac, omf, sqf2, twof, gcoef, hb, abs_z, mass2, sqA, dt_max, diff_frac,
+        adv_frac;
     double rb, inv_shell;
     uint32_t seed_lo, seed_hi, job_tag, step_cap;
     int32_t nreg, drift, hcs;
@@ -175,16 +189,18 @@ __device__ __forceinline__ JobReg<R> load_job(const JobDev<R>& J)
     JobReg<R> o;
     o.vf = J.vf;
     o.omega = J.omega;
-    o.kperp_frac = J.kperp_frac;
+    o.kfrac = J.kperp_frac;
+    o.omf = J.omf;
+    o.sqf2 = J.sqf2;
+    o.twof = J.twof;
     o.gcoef = J.gcoef;
-    o.br0 = J.br0;
+    o.hb = J.hb;
     o.abs_z = J.abs_z;
     o.mass2 = J.mass2;
     o.sqA = J.sqA;
     o.dt_max = J.dt_max;
     o.diff_frac = J.diff_frac;
     o.adv_frac = J.adv_frac;
-    o.rlcoef = J.rlcoef;
     o.rb = J.rb;
     o.inv_shell = J.inv_shell;
     o.seed_lo = J.seed_lo;
@@ -204,6 +220,10 @@ __device__ __forceinline__ int region_of(const JobReg<R>& J, double r)
     return k < J.nreg - 1 ? k : J.nreg - 1;
 }
 
+// Local coefficients, written to share every common factor:
+//   g = 1/(1+Gamma^2) = V^2/(V^2+w^2), Gamma g = V w/(V^2+w^2), Gamma^2 g = 1 - g
+//   (w = Omega r sin(theta)), B from one reciprocal square root of 2 K_rr with
+//   B_phiphi = 2 sqrt(kperp/kpar) kpar / sqrt(2 K_rr), B_thth = sqrt(2 kperp).
 template <typename R, bool FULL>
 __device__ __forceinline__ void coeffs3d(const JobReg<R>& J, const RegionDev<R>& g, double rd,
                                          double Pd, R th, R ph, Coef3<R>& c)
@@ -218,86 +238,95 @@ __device__ __forceinline__ void coeffs3d(const JobReg<R>& J, const RegionDev<R>&
     const R invr = M::rcp(r);
     const R invst = M::rcp(st);
     const R cot = ct * invst;
+    const R irs = invr * invst;
     // wind: slow inside |latitude| <= tilt of the shell, fast outside
     const R lam = (R)(0.5 * kPi) - th;
     const R V = (fabs(lam) <= g.alpha) ? g.vs : J.vf;
     // diffusion tensor: k_par along b ~ (1, 0, -Gamma), k_perp across
     const R pc = J.abs_z * P;
     const R beta = pc * M::rsqrt(pc * pc + J.mass2);
-    const R kpar = g.k0 * beta * P;
-    const R kperp = J.kperp_frac * kpar;
-    const R dk = kpar - kperp;
-    const R w = J.omega * r * st;  // corotation speed; Gamma = w / V
+    const R bP = beta * P;
+    const R kpar = g.k0 * bP;
+    const R kperp = J.kfrac * kpar;
+    const R dk = J.omf * kpar;
+    const R w = (J.omega * r) * st;  // corotation speed; Gamma = w / V
     const R V2 = V * V;
-    const R invD = M::rcp(V2 + w * w);
-    const R gq = V2 * invD;       // 1 / (1 + Gamma^2)
-    const R Gg = V * w * invD;    // Gamma / (1 + Gamma^2)
-    const R GGg = w * w * invD;   // Gamma^2 / (1 + Gamma^2)
-    const R Krr = kperp + dk * gq;
+    const R invD = M::rcp(w * w + V2);
+    const R gq = V2 * invD;          // 1 / (1 + Gamma^2)
+    const R Gg = (V * invD) * w;     // Gamma / (1 + Gamma^2)
+    const R GGg = (R)1.0 - gq;       // Gamma^2 / (1 + Gamma^2)
+    const R Krr = dk * gq + kperp;
     const R Krp = -dk * Gg;
     // d/dr K_rr and (1/r) d/dr (r K_rphi), Gamma proportional to r
-    const R dKrr = (R)-2.0 * dk * GGg * gq * invr;
-    const R dKrp = (R)-2.0 * dk * Gg * gq * invr;
+    const R q = ((R)-2.0 * dk * invr) * gq;
+    const R dKrr = q * GGg;
+    const R dKrp = q * Gg;
+    const R rr = r * r;
 
     R vdr = 0, vdt = 0, vdp = 0, Hw = 1;
     if (J.drift) {
         const R invV = M::rcp(V);
         const R Gam = w * invV;
         const R Gam2 = Gam * Gam;
-        const R opg = (R)1.0 + Gam2;
-        const R gg = M::rcp(opg);
-        // kappa_A / sqrt(1 + Gamma^2), kappa_A = beta P / (3 |B|)
-        const R G = J.gcoef * beta * P * r * r * gg;
+        // kappa_A / sqrt(1 + Gamma^2) with kappa_A = beta P / (3 |B|)
+        const R G = (J.gcoef * bP) * (rr * gq);
+        const R Gcot = Gam * cot;
+        const R G2cot = Gam * Gcot;
         R vcr = 0, vct = 0, vcp = 0;
         if (J.hcs) {
             // wavy sheet: latitude atan(tan(alpha) sin(phi + Omega r / Vs)),
             // polarity factor tanh((theta_cs - theta) / Delta), Delta = 2 r_L / r
             R sc, cc;
-            M::sincos_rad(ph + g.om_vs * r, &sc, &cc);
-            const R tana = g.tana;
-            const R u = lam - M::atan(tana * sc);
-            const R Bmag = J.br0 * invr * invr * M::sqrt(opg);
-            const R invDelta = r * Bmag * M::rcp((R)2.0 * J.rlcoef * P);
+            M::sincos_rad(g.om_vs * r + ph, &sc, &cc);
+            const R y = g.tana * sc;
+            const R u = lam - M::atan(y);
+            // 1/Delta = r |B| / (2 r_L coefficient P), |B| = br0 sqrt(1+Gamma^2) / r^2
+            const R invDelta = (J.hb * M::sqrt((R)1.0 + Gam2)) * (invr * M::rcp(P));
             Hw = M::tanh(u * invDelta);
             const R Hp = (R)1.0 - Hw * Hw;
-            const R cs = -tana * cc * M::rcp((R)1.0 + tana * tana * sc * sc);
-            const R gr = cs * g.om_vs;          // d theta_cs / dr
-            const R gph = cs * invr * invst;    // (1/(r sin)) d theta_cs / dphi
+            const R cs = (-g.tana * cc) * M::rcp(y * y + (R)1.0);
+            const R gr = cs * g.om_vs;  // d theta_cs / dr
+            const R gph = cs * irs;     // (1/(r sin)) d theta_cs / dphi
             // grad Hw x W, grad Hw = (Hp/Delta)(grad u - u grad ln Delta)
-            const R f = Hp * invDelta * G;
-            const R ug = u * gg * invr;
-            vcr = f * (Gam * invr - ug * Gam * Gam2 * cot);
-            vct = f * (gph + gr * Gam - ug * Gam);
-            vcp = f * (invr - ug * Gam2 * cot);
+            const R f = (Hp * invDelta) * G;
+            const R ug = (u * gq) * invr;
+            vcr = f * (-ug * (Gam * G2cot) + Gam * invr);
+            vct = f * (Gam * (gr - ug) + gph);
+            vcp = f * (-ug * G2cot + invr);
         }
-        // gradient-curvature drift Hw curl(G (1, 0, -Gamma))
-        const R twoGg = (R)2.0 * G * gg;
-        vdr = J.sqA * (Hw * (-twoGg * J.omega * invV * ct) + vcr);
-        vdt = J.sqA * (Hw * (twoGg * Gam * ((R)2.0 + Gam2) * invr) + vct);
-        vdp = J.sqA * (Hw * (twoGg * Gam2 * cot * invr) + vcp);
+        // gradient-curvature drift Hw curl(G (1, 0, -Gamma)):
+        // 2 G g / r (-Gamma cot, Gamma (2 + Gamma^2), Gamma^2 cot)
+        const R hA = Hw * (((G + G) * gq) * invr);
+        vdr = J.sqA * (-hA * Gcot + vcr);
+        vdt = J.sqA * ((hA * Gam) * (Gam2 + (R)2.0) + vct);
+        vdp = J.sqA * (hA * G2cot + vcp);
     }
-    c.Ar = (R)2.0 * Krr * invr + dKrr - V - vdr;
-    c.At = kperp * cot * invr * invr - vdt * invr;
-    c.Ap = (dKrp - vdp) * invr * invst;
-    c.AP = (R)(2.0 / 3.0) * V * P * invr;
+    c.Ar = ((Krr + Krr) * invr + dKrr) - V - vdr;
+    c.At = invr * ((kperp * cot) * invr - vdt);
+    c.Ap = (dKrp - vdp) * irs;
+    c.AP = ((V * P) * invr) * (R)(2.0 / 3.0);
     // time step: min(dt_max, f_diff r^2 / k_par, f_adv r / |A_det|)
     R dt = J.dt_max;
-    const R d1 = J.diff_frac * r * r * M::rcp(kpar);
+    const R d1 = (J.diff_frac * rr) * M::rcp(kpar);
     dt = d1 < dt ? d1 : dt;
     if (J.adv_frac > (R)0) {
         const R at = r * c.At;
-        const R ap = r * st * c.Ap;
-        const R a2 = c.Ar * c.Ar + at * at + ap * ap;
+        const R ap = (r * st) * c.Ap;
+        const R a2 = c.Ar * c.Ar + (at * at + ap * ap);
         if (a2 > (R)0) {
-            const R d2 = J.adv_frac * r * M::rsqrt(a2);
+            const R d2 = (J.adv_frac * r) * M::rsqrt(a2);
             dt = d2 < dt ? d2 : dt;
         }
     }
     c.dt = dt;
-    c.Brr = M::sqrt((R)2.0 * Krr);
-    c.Bpr = (R)2.0 * Krp * M::rcp(c.Brr);
-    c.Bpp = M::sqrt((R)2.0 * kpar * kperp * M::rcp(Krr));
-    c.Btt = M::sqrt((R)2.0 * kperp);
+    const R tK = Krr + Krr;
+    const R rs = M::rsqrt(tK);
+    c.Brr = tK * rs;
+    c.Bpr = (Krp + Krp) * rs;
+    c.Bpp = (J.sqf2 * kpar) * rs;
+    c.Btt = M::sqrt(J.twof * kpar);
+    c.invr = invr;
+    c.invst = invst;
     if (FULL) {
         c.Hw = Hw;
         c.vdr = vdr;
@@ -309,29 +338,37 @@ __device__ __forceinline__ void coeffs3d(const JobReg<R>& J, const RegionDev<R>&
     }
 }
 
-// One EM step of the 3D model.  Returns nothing; the caller tests r >= rb.
-template <typename R>
+// One EM step of the 3D model.  The caller tests r >= rb.
+template <typename R, bool UKEY>
 __device__ __forceinline__ void step3d(const JobReg<R>& J, const RegionDev<R>* __restrict__ reg,
-                                       PState<R>& s, uint32_t pid, uint32_t bin)
+                                       PState<R>& s, uint32_t pid, uint32_t bin, uint32_t k0,
+                                       uint32_t k1)
 {
     using M = Mth<R>;
     R z[3];
-    normals<R, 3>(J.seed_lo, J.seed_hi, s.n, pid, bin, J.job_tag, z);
+    normals<R, 3>(UKEY ? k0 : J.seed_lo, UKEY ? k1 : J.seed_hi, s.n, pid, bin, J.job_tag, z);
     const RegionDev<R> g = reg[region_of(J, s.r)];
     Coef3<R> c;
     coeffs3d<R, false>(J, g, s.r, s.P, s.th, s.ph, c);
     const R dt = c.dt;
     const R sdt = M::sqrt(dt);
-    const R r0 = (R)s.r;
-    const R r = r0 > M::kRFloor ? r0 : M::kRFloor;
-    const R invr = M::rcp(r);
-    R st, ct;
-    M::sincos_rad(s.th, &st, &ct);
-    st = st > M::kSinFloor ? st : M::kSinFloor;
-    double r1 = s.r + (double)(c.Ar * dt) + (double)(c.Brr * z[0] * sdt);
-    R th1 = s.th + c.At * dt + c.Btt * z[2] * sdt * invr;
-    R ph1 = s.ph + c.Ap * dt + (c.Bpr * z[0] + c.Bpp * z[1]) * sdt * (invr * M::rcp(st));
-    const double P1 = s.P + (double)(c.AP * dt);
+    double r1;
+    R th1, ph1;
+    double P1;
+    if constexpr (std::is_same<R, float>::value) {
+        // binary32 increments, accumulated into the binary64 r, P, t
+        const float sdi = sdt * c.invr;
+        r1 = s.r + (double)((c.Brr * z[0]) * sdt + c.Ar * dt);
+        th1 = (c.Btt * z[2]) * sdi + (c.At * dt + s.th);
+        ph1 = (c.Bpr * z[0] + c.Bpp * z[1]) * (sdi * c.invst) + (c.Ap * dt + s.ph);
+        P1 = s.P + (double)(c.AP * dt);
+    } else {
+        // same association of terms as a plain left-to-right evaluation
+        r1 = s.r + c.Ar * dt + c.Brr * z[0] * sdt;
+        th1 = s.th + c.At * dt + c.Btt * z[2] * sdt * c.invr;
+        ph1 = s.ph + c.Ap * dt + (c.Bpr * z[0] + c.Bpp * z[1]) * sdt * (c.invr * c.invst);
+        P1 = s.P + c.AP * dt;
+    }
     if (r1 < 0.0) {
         r1 = -r1;
         th1 = (R)kPi - th1;
@@ -361,13 +398,14 @@ __device__ __forceinline__ void step3d(const JobReg<R>& J, const RegionDev<R>* _
 }
 
 // One EM step of the radial model: dr = (2k/r - V) ds + sqrt(2k) dW.
-template <typename R>
+template <typename R, bool UKEY>
 __device__ __forceinline__ void step1d(const JobReg<R>& J, const RegionDev<R>* __restrict__ reg,
-                                       PState<R>& s, uint32_t pid, uint32_t bin)
+                                       PState<R>& s, uint32_t pid, uint32_t bin, uint32_t k0,
+                                       uint32_t k1)
 {
     using M = Mth<R>;
     R z[1];
-    normals<R, 1>(J.seed_lo, J.seed_hi, s.n, pid, bin, J.job_tag, z);
+    normals<R, 1>(UKEY ? k0 : J.seed_lo, UKEY ? k1 : J.seed_hi, s.n, pid, bin, J.job_tag, z);
     const RegionDev<R> g = reg[region_of(J, s.r)];
     const R r0 = (R)s.r;
     const R r = r0 > M::kRFloor ? r0 : M::kRFloor;
@@ -407,7 +445,7 @@ __device__ __forceinline__ uint32_t wave_uniform(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
-template <typename R, bool M3D>
+template <typename R, bool M3D, bool UKEY>
 __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
 {
     const uint32_t lane = __lane_id();
@@ -520,9 +558,9 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
                 done = true;
             } else {
                 if (M3D)
-                    step3d<R>(J, reg, s, pid, bin);
+                    step3d<R, UKEY>(J, reg, s, pid, bin, a.key_lo, a.key_hi);
                 else
-                    step1d<R>(J, reg, s, pid, bin);
+                    step1d<R, UKEY>(J, reg, s, pid, bin, a.key_lo, a.key_hi);
                 ++budget;
                 if (!(s.r == s.r) || !(s.P == s.P)) {
                     flags = kFlagNaN;
@@ -567,7 +605,11 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
 template <typename R, bool M3D>
 static hipError_t launch_prop(const PropArgs<R>& a, int grid, int block, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_propagate<R, M3D>), dim3(grid), dim3(block), 0, s, a);
+    // one Philox key for the whole launch: the key schedule runs on the scalar unit
+    if (a.uniform_key)
+        hipLaunchKernelGGL((k_propagate<R, M3D, true>), dim3(grid), dim3(block), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_propagate<R, M3D, false>), dim3(grid), dim3(block), 0, s, a);
     return hipGetLastError();
 }
 
@@ -590,13 +632,32 @@ hipError_t launch_propagate_1d_fp64(const PropArgs<double>& a, int grid, int blo
 
 hipError_t occupancy_propagate(int model, int prec, int block, int* blocks_per_cu)
 {
-    const void* f = nullptr;
-    if (model == 1 && prec == 1) f = (const void*)&k_propagate<float, true>;
-    if (model == 1 && prec == 0) f = (const void*)&k_propagate<double, true>;
-    if (model == 0 && prec == 1) f = (const void*)&k_propagate<float, false>;
-    if (model == 0 && prec == 0) f = (const void*)&k_propagate<double, false>;
-    if (f == nullptr) return hipErrorInvalidValue;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, 0);
+    const void* f[2] = {nullptr, nullptr};
+    if (model == 1 && prec == 1) {
+        f[0] = (const void*)&k_propagate<float, true, false>;
+        f[1] = (const void*)&k_propagate<float, true, true>;
+    } else if (model == 1 && prec == 0) {
+        f[0] = (const void*)&k_propagate<double, true, false>;
+        f[1] = (const void*)&k_propagate<double, true, true>;
+    } else if (model == 0 && prec == 1) {
+        f[0] = (const void*)&k_propagate<float, false, false>;
+        f[1] = (const void*)&k_propagate<float, false, true>;
+    } else if (model == 0 && prec == 0) {
+        f[0] = (const void*)&k_propagate<double, false, false>;
+        f[1] = (const void*)&k_propagate<double, false, true>;
+    } else {
+        return hipErrorInvalidValue;
+    }
+    // the smaller residency of the two key variants, so either fits the grid
+    int lo = 1 << 30;
+    for (const void* fn : f) {
+        int n = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, 0);
+        if (e != hipSuccess) return e;
+        lo = n < lo ? n : lo;
+    }
+    *blocks_per_cu = lo;
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

@@ -157,16 +157,20 @@ void make_tables(const JobCopy& jc, JobDev<R>* J, RegionDev<R>* reg, LisDev* lis
     J->vf = (R)(h.v_fast_km_s / kAuKm);
     J->omega = (R)h.omega_rad_s;
     J->kperp_frac = (R)h.kperp_over_kpar;
+    J->omf = (R)(1.0 - h.kperp_over_kpar);
+    J->sqf2 = (R)(2.0 * std::sqrt(h.kperp_over_kpar));
+    J->twof = (R)(2.0 * h.kperp_over_kpar);
     // |B| at 1 AU on the ecliptic is b0 for a wind of v_ref: B_r(1 AU) = b0 / sqrt(1 + Gamma_E^2)
     double br0 = h.b0_nT;
     if (h.v_ref_km_s > 0.0) {
         const double gE = h.omega_rad_s * kAuKm / h.v_ref_km_s;
         br0 = h.b0_nT / std::sqrt(1.0 + gE * gE);
     }
-    J->br0 = (R)br0;
     // kappa_A = beta P / (3 |B|) [GV, nT -> AU^2/s], |B| = br0 / r^2 * sqrt(1 + Gamma^2)
     J->gcoef = br0 > 0.0 ? (R)(1e18 / (3.0 * br0 * kAuM * kAuM)) : (R)0;
-    J->rlcoef = (R)(1e18 / (kLightMs * kAuM));
+    // sheet half-width Delta = 2 r_L / r with r_L = P / (c |B|) [GV, nT -> AU]
+    const double rlcoef = 1e18 / (kLightMs * kAuM);
+    J->hb = (R)(br0 / (2.0 * rlcoef));
     J->abs_z = (R)std::fabs((double)s.charge);
     J->mass2 = (R)(s.mass_gev * s.mass_gev);
     J->sqA = (R)((s.charge > 0 ? 1.0 : -1.0) * (double)h.polarity);
@@ -376,6 +380,8 @@ struct cosmica_plan {
     uint32_t* nnan = nullptr;
     bool executed = false;
     bool own_out = true;
+    bool uniform_key = false;  // every job has the same seed
+    uint64_t key = 0;
     explicit cosmica_plan(cosmica_ctx* c) : ctx(c), mem(c) {}
 };
 
@@ -439,6 +445,9 @@ cosmica_status execute_prop(cosmica_plan* p)
         a.job_done = nullptr;
         a.leftover = nullptr;
         a.leftover_count = p->counters_d + 4;
+        a.uniform_key = p->uniform_key ? 1u : 0u;
+        a.key_lo = (uint32_t)(p->key & 0xffffffffu);
+        a.key_hi = (uint32_t)(p->key >> 32);
         const int grid = grid_for(ctx, model, p->prec, L, p->model_particles[model]);
         ctx->timings.grid_blocks = grid;
         ctx->timings.block = L.block;
@@ -547,6 +556,9 @@ cosmica_status cosmica_plan_create(cosmica_ctx* ctx, const cosmica_job* jobs, in
         const cosmica_launch& L = ctx->launch[m][precision];
         make_chunks(p->segs, ids[m], L.chunk, L.order, &p->chunks_h[m]);
     }
+    p->key = p->jobs[0].seed;
+    p->uniform_key = true;
+    for (const JobCopy& jc : p->jobs) p->uniform_key &= jc.seed == p->key;
     cosmica_status st = precision == COSMICA_PREC_MIXED ? upload_tables<float>(p.get())
                                                          : upload_tables<double>(p.get());
     if (st != COSMICA_OK) return st;
