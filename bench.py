@@ -40,12 +40,12 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2502_06319_amd", "csrc", "kernels.hip")
 # formulas the kernels evaluate (each add, multiply, fused multiply-add,
 # compare/select, conversion, integer op and hardware transcendental = 1).
 OPS_PER_STEP = {
-    "3d": {"philox4x32_10": 80, "uniforms": 16, "box_muller": 12, "region_geometry": 13,
-           "beta_kappa": 9, "spiral_weights": 10, "tensor_and_divergence": 10,
-           "drift_prelude": 9, "current_sheet": 44, "gradient_curvature": 20,
-           "drift_vector": 14, "time_step": 15, "tensor_sqrt": 12, "em_update": 31},
-    "1d": {"philox4x32_10": 80, "uniforms": 8, "box_muller": 5, "region": 3,
-           "beta_kappa": 7, "coefficients": 12, "time_step": 5, "em_update": 13},
+    "3d": {"philox4x32_10": 80, "uniforms": 12, "box_muller": 12, "region_geometry": 15,
+           "beta_kappa": 8, "spiral_weights": 9, "tensor_and_divergence": 8,
+           "drift_prelude": 8, "current_sheet": 35, "gradient_curvature": 12,
+           "drift_vector": 12, "time_step": 17, "tensor_sqrt": 9, "em_update": 30},
+    "1d": {"philox4x32_10": 80, "uniforms": 6, "box_muller": 5, "region_geometry": 5,
+           "beta_kappa": 6, "coefficients": 8, "time_step": 6, "em_update": 19},
 }
 # Peak VALU lane-operation issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz =
 # 39.3 T lane-ops/s, for FP32 without packed math (the published 157.3 TFLOP/s
