@@ -230,7 +230,8 @@ cosmica_status cosmica_get_launch(cosmica_ctx* ctx, cosmica_model model,
 /* Times a calibration batch over candidate launch shapes and keeps the fastest
  * for (model, precision) (the paper's warps-per-block sweep, Sec. VI "Version 2",
  * generalised).  cache_path, if not NULL, is read first (a hit skips the sweep)
- * and updated afterwards; the cache key includes the device architecture. */
+ * and updated afterwards; the cache key includes the device architecture and
+ * a digest of the kernel source the library was built from. */
 cosmica_status cosmica_tune(cosmica_ctx* ctx, cosmica_model model, cosmica_precision precision,
                             const char* cache_path);
 

@@ -5,6 +5,7 @@ disabled (-packed-fp32-ops): the arithmetic is scalar per particle.
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -25,13 +26,23 @@ def hipcc() -> str:
     return h
 
 
+def kernel_id() -> str:
+    """Digest of the device code (kernels.hip and engine.hpp); the autotuner
+    keys its cache on it."""
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "engine.hpp"):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False, jobs: int = 2) -> str:
     cc = hipcc()
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     common = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", INCLUDE, "-I", CSRC,
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-              "-Wall", "-Wno-unused-function"]
+              "-Wall", "-Wno-unused-function", f'-DCOSMICA_KERNEL_ID="{kernel_id()}"']
     objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")

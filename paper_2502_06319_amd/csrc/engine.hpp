@@ -91,7 +91,7 @@ struct PropArgs {
     uint32_t* resume_head;        // cursor over the resume list, zeroed before launch
     SuspendDev* suspend;
     uint32_t* suspend_count;      // zeroed before launch
-    uint32_t step_budget;         // steps per lane per launch (0xffffffff: unlimited)
+    uint32_t step_budget;         // steps per wave per launch (0xffffffff: unlimited)
     uint32_t uniform_key;         // 1: every job of the launch has the Philox key below
     uint32_t key_lo, key_hi;
     const uint32_t* job_cancel;   // optional per-job cancel flags

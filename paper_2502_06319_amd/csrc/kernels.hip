@@ -27,8 +27,16 @@ constexpr double kTwoPi = 6.283185307179586476925286766559005768;
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11 -- the generator of Sec. IV.A).  Written
-// for gfx950: each 32x32->64 product is one v_mad_u64_u32.
+// for gfx950: each 32x32->64 product is one v_mad_u64_u32 and each three-way
+// XOR one v_bitop3_b32, so a round is two of each.
 // ---------------------------------------------------------------------------
+// a ^ b ^ c: truth table 0x96 sets the output bit where an odd number of the
+// three input bits is set.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox4x32_10(uint32_t k0, uint32_t k1, uint32_t c0,
                                                uint32_t c1, uint32_t c2, uint32_t c3)
 {
@@ -36,8 +44,8 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t k0, uint32_t k1, uint32_
     for (int i = 0; i < 10; ++i) {
         const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(m1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(m0 >> 32), c3, k1);
         c1 = (uint32_t)m1;
         c3 = (uint32_t)m0;
         c0 = n0;
@@ -454,7 +462,9 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
     JobReg<R> J = {};
     const RegionDev<R>* reg = a.regions;
     bool active = false;
-    uint32_t budget = 0;  // steps this lane has taken in this launch
+    // steps this wave has taken in this launch (wave-uniform) and its limit
+    uint64_t wave_steps = 0;
+    const uint64_t step_budget = a.step_budget == 0xffffffffu ? ~0ull : (uint64_t)a.step_budget;
 
     // wave-uniform refill cursors
     uint32_t c_seg = 0, c_next = 0, c_end = 0;
@@ -548,40 +558,50 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
             break;
         }
 
-        if (active) {
-            uint32_t flags = 0;
-            bool done = false;
-            if (a.job_cancel != nullptr && a.job_cancel[job] != 0u) {
-                active = false;  // dropped: no record
-            } else if (s.n >= J.step_cap) {
-                flags = kFlagCapped;
-                done = true;
-            } else {
+        // a cancelled job's particles are dropped without a record
+        if (active && a.job_cancel != nullptr && a.job_cancel[job] != 0u) active = false;
+        if (!__any(active)) continue;
+
+        // Advance the active lanes in lockstep until one of them leaves (boundary
+        // crossing, step cap or non-finite state) or the slice's step budget is
+        // spent.  The loop carries only the particle state, so it stays in place.
+        uint32_t flags = 0;
+        bool done = false;
+        for (;;) {
+            if (active) {
                 if (M3D)
                     step3d<R, UKEY>(J, reg, s, pid, bin, a.key_lo, a.key_hi);
                 else
                     step1d<R, UKEY>(J, reg, s, pid, bin, a.key_lo, a.key_hi);
-                ++budget;
                 if (!(s.r == s.r) || !(s.P == s.P)) {
                     flags = kFlagNaN;
                     done = true;
                 } else if (s.r >= J.rb) {
                     done = true;
+                } else if (s.n >= J.step_cap) {
+                    flags = kFlagCapped;
+                    done = true;
                 }
             }
-            if (done) {
-                a.exP[out] = s.P;
-                a.exT[out] = s.t;
-                a.exNF[out] = s.n | (flags << kFlagShift);
-                if (a.exR != nullptr) {
-                    a.exR[out] = s.r;
-                    a.exTh[out] = (double)s.th;
-                    a.exPh[out] = (double)s.ph;
-                }
-                if (a.job_done != nullptr) atomicAdd(&a.job_done[job], 1u);
-                active = false;
-            } else if (active && budget >= a.step_budget) {
-                // slice over: park the particle for the next launch
+            ++wave_steps;
+            if (__any(done) || wave_steps >= step_budget) break;
+        }
+        if (done) {
+            a.exP[out] = s.P;
+            a.exT[out] = s.t;
+            a.exNF[out] = s.n | (flags << kFlagShift);
+            if (a.exR != nullptr) {
+                a.exR[out] = s.r;
+                a.exTh[out] = (double)s.th;
+                a.exPh[out] = (double)s.ph;
+            }
+            if (a.job_done != nullptr) atomicAdd(&a.job_done[job], 1u);
+            active = false;
+        }
+        if (wave_steps >= step_budget) {
+            // slice over: park the wave's particles for the next launch and stop
+            // taking work
+            if (active) {
                 const uint32_t slot = atomicAdd(a.suspend_count, 1u);
                 SuspendDev q;
                 q.r = s.r;
@@ -596,9 +616,8 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
                 a.suspend[slot] = q;
                 active = false;
             }
+            launch_open = false;
         }
-        // a wave stops taking work once one of its lanes used up the budget
-        if (a.step_budget != 0xffffffffu && __any(budget >= a.step_budget)) launch_open = false;
     }
 }
 

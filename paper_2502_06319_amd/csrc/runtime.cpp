@@ -947,9 +947,15 @@ void make_calibration(int model, uint32_t per_bin, Calib* c)
                          0u, 0u};  // tag 0, seed 12345, default cap, bin offset 0
 }
 
+#ifndef COSMICA_KERNEL_ID
+#define COSMICA_KERNEL_ID "unversioned"
+#endif
+
+// Device architecture plus the digest of the kernel source the library was
+// built from: a launch shape tuned for other kernel code is not reused.
 std::string tune_key(cosmica_ctx* ctx, int model, int prec)
 {
-    std::string a = ctx->arch;
+    std::string a = ctx->arch + "@" + COSMICA_KERNEL_ID;
     for (char& ch : a)
         if (ch == ' ') ch = '_';
     return a + " " + std::to_string(model) + " " + std::to_string(prec);
