@@ -114,10 +114,12 @@ struct Mth<double> {
 
 // Uniform in (0,1): (floor(x / 2^9) + 1/2) * 2^-23, exact in binary32 and
 // binary64.  In binary32 it is built from the bits: 1 + floor(x/2^9) 2^-23 has
-// the 23 bits as mantissa, and subtracting 1 - 2^-24 is exact.
+// the 23 bits as mantissa, and subtracting 1 - 2^-24 is exact.  The pattern
+// 0x3F800000 | (x >> 9) is one v_alignbit_b32: the 64-bit pair (0x7F, x)
+// shifted right by 9.
 __device__ __forceinline__ float uniform_f32(uint32_t x)
 {
-    return __uint_as_float((x >> 9) | 0x3F800000u) - 0.99999994039535522f;
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, x, 9u)) - 0.99999994039535522f;
 }
 __device__ __forceinline__ double uniform_f64(uint32_t x)
 {
@@ -221,6 +223,7 @@ __device__ __forceinline__ JobReg<R> load_job(const JobDev<R>& J)
     return o;
 }
 
+// Shell index of r (r >= 0 after the reflections), clamped to the last shell.
 template <typename R>
 __device__ __forceinline__ int region_of(const JobReg<R>& J, double r)
 {
@@ -462,9 +465,10 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
     JobReg<R> J = {};
     const RegionDev<R>* reg = a.regions;
     bool active = false;
-    // steps this wave has taken in this launch (wave-uniform) and its limit
-    uint64_t wave_steps = 0;
-    const uint64_t step_budget = a.step_budget == 0xffffffffu ? ~0ull : (uint64_t)a.step_budget;
+    // steps this wave has taken in this launch (wave-uniform), counted against
+    // a.step_budget when the launch is a slice
+    uint32_t wave_steps = 0;
+    const bool sliced = a.step_budget != 0xffffffffu;
 
     // wave-uniform refill cursors
     uint32_t c_seg = 0, c_next = 0, c_end = 0;
@@ -563,30 +567,28 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
         if (!__any(active)) continue;
 
         // Advance the active lanes in lockstep until one of them leaves (boundary
-        // crossing, step cap or non-finite state) or the slice's step budget is
-        // spent.  The loop carries only the particle state, so it stays in place.
-        uint32_t flags = 0;
-        bool done = false;
+        // crossing, non-finite state or step cap) or the slice's step budget is
+        // spent.  The loop carries only the particle state, so it stays in place;
+        // why a lane left is worked out afterwards from its state.
         for (;;) {
+            bool leave = false;
             if (active) {
                 if (M3D)
                     step3d<R, UKEY>(J, reg, s, pid, bin, a.key_lo, a.key_hi);
                 else
                     step1d<R, UKEY>(J, reg, s, pid, bin, a.key_lo, a.key_hi);
-                if (!(s.r == s.r) || !(s.P == s.P)) {
-                    flags = kFlagNaN;
-                    done = true;
-                } else if (s.r >= J.rb) {
-                    done = true;
-                } else if (s.n >= J.step_cap) {
-                    flags = kFlagCapped;
-                    done = true;
-                }
+                // !(r < rb) also holds for a NaN r
+                leave = !(s.r < J.rb) || !(s.P == s.P) || s.n >= J.step_cap;
             }
             ++wave_steps;
-            if (__any(done) || wave_steps >= step_budget) break;
+            if (__any(leave) || (sliced && wave_steps >= a.step_budget)) break;
         }
-        if (done) {
+        if (active && (!(s.r < J.rb) || !(s.P == s.P) || s.n >= J.step_cap)) {
+            uint32_t flags = 0;
+            if (!(s.r == s.r) || !(s.P == s.P))
+                flags = kFlagNaN;
+            else if (!(s.r >= J.rb))
+                flags = kFlagCapped;
             a.exP[out] = s.P;
             a.exT[out] = s.t;
             a.exNF[out] = s.n | (flags << kFlagShift);
@@ -598,7 +600,7 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
             if (a.job_done != nullptr) atomicAdd(&a.job_done[job], 1u);
             active = false;
         }
-        if (wave_steps >= step_budget) {
+        if (sliced && wave_steps >= a.step_budget) {
             // slice over: park the wave's particles for the next launch and stop
             // taking work
             if (active) {

@@ -157,7 +157,7 @@ def test_full_size_batched_mixed(eng, orc, W, othreads):
     from bench import tuned_engine_launch
 
     jobs = W.c4_jobs()
-    tuned_engine_launch(eng, jobs)
+    tuned_engine_launch(eng, {"mixed": jobs})
     plan = eng.plan(jobs, "mixed", exits=True)
     plan.execute()
     res = plan.read(exits=True)
