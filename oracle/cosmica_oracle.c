@@ -105,14 +105,22 @@ void orc_rng_block(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_
 /* ------------------------------------------------------------------------ */
 /* Per-job constants in internal units.                                      */
 /* ------------------------------------------------------------------------ */
+/* Parameter regions: the radial shells 0..nreg-1 and, when the heliosheath
+ * is on, the heliosheath as entry nreg. */
+#define ORC_REGION_SLOTS (ORC_MAX_REGIONS + 1)
+
 typedef struct {
     int nreg;
     double Rb, shell;
-    double k0[ORC_MAX_REGIONS];    /* kappa0 [AU^2/s] */
-    double vs[ORC_MAX_REGIONS];    /* slow wind [AU/s] */
-    double alpha[ORC_MAX_REGIONS]; /* tilt [rad] */
-    double tana[ORC_MAX_REGIONS];
-    double vf;                     /* fast wind [AU/s] */
+    double Rb_nose;                /* heliopause toward the nose (== Rb: spherical) */
+    int hs;                        /* heliosheath on */
+    double ts_nose, ts_tail;       /* termination shock */
+    double nose[3];                /* unit vector toward the nose */
+    double k0[ORC_REGION_SLOTS];    /* kappa0 [AU^2/s] */
+    double vs[ORC_REGION_SLOTS];    /* slow wind [AU/s] */
+    double vf[ORC_REGION_SLOTS];    /* fast wind [AU/s] */
+    double alpha[ORC_REGION_SLOTS]; /* tilt [rad] */
+    double tana[ORC_REGION_SLOTS];
     double Br0;                    /* radial field at 1 AU [nT] */
     double absZ, mass;
     double sqA;                    /* sign(Z) * A */
@@ -125,14 +133,35 @@ static int derive(const orc_params* p, derived* d)
     if (p->charge == 0 || !(p->mass_gev >= 0.0)) return -1;
     d->nreg = p->n_regions;
     d->Rb = p->r_boundary_au;
-    d->shell = p->r_boundary_au / (double)p->n_regions;
+    d->Rb_nose = p->r_boundary_nose_au > 0.0 ? p->r_boundary_nose_au : p->r_boundary_au;
+    if (!(d->Rb_nose <= d->Rb) || !(d->Rb_nose > p->r0_au)) return -1;
+    d->hs = p->heliosheath != 0;
+    if (p->model == 0 && (d->hs || d->Rb_nose != d->Rb)) return -1; /* 3D only */
+    d->ts_nose = p->ts_nose_au;
+    d->ts_tail = p->ts_tail_au;
+    if (d->hs && !(d->ts_nose > p->r0_au && d->ts_nose <= d->ts_tail)) return -1;
+    d->nose[0] = sin(p->nose_theta_rad) * cos(p->nose_phi_rad);
+    d->nose[1] = sin(p->nose_theta_rad) * sin(p->nose_phi_rad);
+    d->nose[2] = cos(p->nose_theta_rad);
+    /* READING: the shells split the inner heliosphere radially in equal widths
+     * up to the boundary's (with a heliosheath: the termination shock's) nose
+     * distance; beyond it the last shell holds up to that surface. */
+    d->shell = (d->hs ? d->ts_nose : d->Rb_nose) / (double)p->n_regions;
     for (int k = 0; k < p->n_regions; ++k) {
         d->k0[k] = p->kappa0_cm2_s[k] / (AU_CM * AU_CM);
         d->vs[k] = p->v_slow_km_s[k] / AU_KM;
+        d->vf[k] = p->v_fast_km_s / AU_KM;
         d->alpha[k] = p->tilt_deg[k] * ORC_PI / 180.0;
         d->tana[k] = tan(d->alpha[k]);
     }
-    d->vf = p->v_fast_km_s / AU_KM;
+    if (d->hs) {
+        const int k = p->n_regions;
+        d->k0[k] = p->kappa0_hs_cm2_s / (AU_CM * AU_CM);
+        d->vs[k] = p->v_hs_km_s / AU_KM;
+        d->vf[k] = p->v_hs_km_s / AU_KM;
+        d->alpha[k] = p->tilt_hs_deg * ORC_PI / 180.0;
+        d->tana[k] = tan(d->alpha[k]);
+    }
     /* READING: b0 is |B| at 1 AU on the ecliptic for a wind of v_ref, so the
      * radial component there is b0 / sqrt(1 + (Omega * 1 AU / v_ref)^2). */
     double gE = (p->v_ref_km_s > 0.0) ? p->omega_rad_s * AU_KM / p->v_ref_km_s : 0.0;
@@ -143,12 +172,42 @@ static int derive(const orc_params* p, derived* d)
     return 0;
 }
 
-static int region_of(const derived* d, double r)
+static int shell_of(const derived* d, double r)
 {
     int k = (int)floor(r / d->shell);
     if (k > d->nreg - 1) k = d->nreg - 1;
     if (k < 0) k = 0;
     return k;
+}
+
+/* READING: a heliospheric surface with distances Rn toward the nose and Rt
+ * toward the tail is the sphere of radius (Rn + Rt)/2 centred (Rt - Rn)/2
+ * behind the Sun, against the nose direction; with Rn == Rt it is the sphere
+ * of radius Rt about the Sun.  A point is outside when its distance from the
+ * centre is at least the radius. */
+static int outside_surface(const derived* d, double Rn, double Rt, double r, double th,
+                           double ph)
+{
+    if (Rn == Rt) return r >= Rt;
+    double a = 0.5 * (Rn + Rt);
+    double delta = 0.5 * (Rt - Rn);
+    double x = r * sin(th) * cos(ph) + delta * d->nose[0];
+    double y = r * sin(th) * sin(ph) + delta * d->nose[1];
+    double z = r * cos(th) + delta * d->nose[2];
+    return x * x + y * y + z * z >= a * a;
+}
+
+/* Parameter region at a point: the heliosheath beyond the termination shock,
+ * else the radial shell. */
+static int region_of(const derived* d, double r, double th, double ph)
+{
+    if (d->hs && outside_surface(d, d->ts_nose, d->ts_tail, r, th, ph)) return d->nreg;
+    return shell_of(d, r);
+}
+
+static int outside_heliopause(const derived* d, double r, double th, double ph)
+{
+    return outside_surface(d, d->Rb_nose, d->Rb, r, th, ph);
 }
 
 /* Particle speed over c for rigidity P: pc = |Z| P, E = sqrt((pc)^2 + M^2). */
@@ -169,13 +228,13 @@ static double beta_of(const derived* d, double P)
 static void coeffs3d(const orc_params* p, const derived* d, double P, double r,
                      double th, double ph, orc_coeffs* c)
 {
-    int k = region_of(d, r);
+    int k = region_of(d, r, th, ph);
     double st = sin(th), ct = cos(th);
     double cot = ct / st;
     /* READING: slow wind inside the band |latitude| <= tilt of the region,
-     * fast wind outside it. */
+     * fast wind outside it (the heliosheath has one speed for both). */
     double lam = 0.5 * ORC_PI - th;
-    double V = (fabs(lam) <= d->alpha[k]) ? d->vs[k] : d->vf;
+    double V = (fabs(lam) <= d->alpha[k]) ? d->vs[k] : d->vf[k];
     double beta = beta_of(d, P);
     double kpar = d->k0[k] * beta * P;
     double kperp = p->kperp_over_kpar * kpar;
@@ -290,6 +349,19 @@ static void coeffs3d(const orc_params* p, const derived* d, double P, double r,
     c->dt = dt;
 }
 
+int orc_locate(const orc_params* p, double r, double theta, double phi, int32_t* region)
+{
+    derived d;
+    *region = -1;
+    if (derive(p, &d) != 0) return -1;
+    if (p->model == 0) {
+        *region = shell_of(&d, r);
+        return r >= d.Rb;
+    }
+    *region = region_of(&d, r, theta, phi);
+    return outside_heliopause(&d, r, theta, phi);
+}
+
 void orc_coeffs_3d(const orc_params* p, double P, double r, double theta, double phi,
                    orc_coeffs* out)
 {
@@ -314,7 +386,7 @@ static void step1d(const orc_params* p, const derived* d, uint32_t bin, uint32_t
     uint32_t ctr[4] = {s->n, particle, bin, p->job_tag};
     double z[4];
     orc_normals(p->seed, ctr, z);
-    int k = region_of(d, s->r);
+    int k = shell_of(d, s->r);
     double beta = beta_of(d, s->P);
     double kap = d->k0[k] * beta * s->P;
     double V = d->vs[k];
@@ -388,7 +460,9 @@ static int run(const orc_params* p, const derived* d, uint32_t bin, uint32_t par
         else
             step3d(p, d, bin, particle, s);
         if (isnan(s->r) || isnan(s->P)) return 3;
-        if (s->r >= d->Rb) return 1; /* READING: no crossing interpolation */
+        /* READING: exit at the first step that ends outside; no crossing
+         * interpolation */
+        if (p->model == 0 ? s->r >= d->Rb : outside_heliopause(d, s->r, s->th, s->ph)) return 1;
     }
     return 0;
 }

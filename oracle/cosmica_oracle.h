@@ -63,6 +63,21 @@ typedef struct {
     uint64_t seed;            /* Philox key */
     uint32_t job_tag;         /* fourth Philox counter word */
     uint32_t step_cap;        /* particles still inside after this many steps are flagged */
+    /* Nose-squashed heliosphere with a heliosheath (3D model only; Sec. II.B
+     * names the two regions and the squashing but gives no shape, so all of
+     * this is a READING).  The heliopause and the termination shock are each a
+     * sphere whose centre sits behind the Sun, on the side opposite the nose
+     * direction (nose_theta, nose_phi); each is fixed by its distances from the
+     * Sun toward the nose and toward the tail.  r_boundary_au above is the
+     * heliopause's tail distance. */
+    double r_boundary_nose_au; /* heliopause toward the nose; <= 0: r_boundary_au (spherical) */
+    double nose_theta_rad, nose_phi_rad;
+    int32_t heliosheath;      /* 1: termination shock and heliosheath region */
+    int32_t pad1;
+    double ts_nose_au, ts_tail_au; /* termination shock distances */
+    /* heliosheath region: diffusion coefficient, one wind speed (no fast/slow
+     * band), current-sheet tilt */
+    double kappa0_hs_cm2_s, v_hs_km_s, tilt_hs_deg;
 } orc_params;
 
 enum { ORC_FLAG_CAPPED = 1, ORC_FLAG_NAN = 2 };
@@ -105,6 +120,11 @@ void orc_normals(uint64_t seed, const uint32_t ctr[4], double z[4]);
  * words[4i..4i+3] and z[4i..4i+3] (either may be NULL). */
 void orc_rng_block(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t n,
                    uint32_t* words, double* z);
+
+/* Where a point lies: returns 1 if it is outside the heliopause (the exit
+ * test), else 0; *region receives the parameter region used there (0..n-1 the
+ * radial shells, n_regions the heliosheath). */
+int orc_locate(const orc_params* p, double r, double theta, double phi, int32_t* region);
 
 /* Local 3D coefficients at (P, r, theta, phi). */
 void orc_coeffs_3d(const orc_params* p, double P, double r, double theta, double phi,

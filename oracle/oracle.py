@@ -61,6 +61,16 @@ class OrcParams(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("job_tag", ctypes.c_uint32),
         ("step_cap", ctypes.c_uint32),
+        ("r_boundary_nose_au", ctypes.c_double),
+        ("nose_theta_rad", ctypes.c_double),
+        ("nose_phi_rad", ctypes.c_double),
+        ("heliosheath", ctypes.c_int32),
+        ("pad1", ctypes.c_int32),
+        ("ts_nose_au", ctypes.c_double),
+        ("ts_tail_au", ctypes.c_double),
+        ("kappa0_hs_cm2_s", ctypes.c_double),
+        ("v_hs_km_s", ctypes.c_double),
+        ("tilt_hs_deg", ctypes.c_double),
     ]
 
 
@@ -123,6 +133,9 @@ def lib():
         L.orc_advance.restype = ctypes.c_int
         L.orc_reduce_bin.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_double, ctypes.c_void_p,
                                      ctypes.c_uint32, ctypes.POINTER(OrcBinResult)]
+        L.orc_locate.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, ctypes.POINTER(ctypes.c_int32)]
+        L.orc_locate.restype = ctypes.c_int
         L.orc_lis.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_double]
         L.orc_lis.restype = ctypes.c_double
         _lib = L
@@ -165,6 +178,15 @@ def params(job: dict, **override) -> OrcParams:
     p.seed = int(override.get("seed", job["seed"])) & (2**64 - 1)
     p.job_tag = int(override.get("job_tag", job["job_tag"]))
     p.step_cap = int(override.get("step_cap", job.get("step_cap", 10_000_000)))
+    p.r_boundary_nose_au = h.get("r_boundary_nose_au", 0.0)
+    p.nose_theta_rad = h.get("nose_theta_rad", 0.5 * np.pi)
+    p.nose_phi_rad = h.get("nose_phi_rad", 0.0)
+    p.heliosheath = int(h.get("heliosheath", 0))
+    p.ts_nose_au = h.get("ts_nose_au", 0.0)
+    p.ts_tail_au = h.get("ts_tail_au", 0.0)
+    p.kappa0_hs_cm2_s = h.get("kappa0_hs_cm2_s", 0.0)
+    p.v_hs_km_s = h.get("v_hs_km_s", 0.0)
+    p.tilt_hs_deg = h.get("tilt_hs_deg", 0.0)
     return p
 
 
@@ -226,6 +248,15 @@ def reduce_bin(p: OrcParams, P0: float, rec: np.ndarray) -> dict:
     return {"hist": np.array(list(r.hist), dtype=np.uint32), "flux": r.flux,
             "flux_se": r.flux_se, "mean_exit_time_s": r.mean_exit_time_s, "steps": r.steps,
             "n_capped": r.n_capped, "n_nan": r.n_nan, "n_used": r.n_used}
+
+
+def locate(p: OrcParams, r: float, theta: float, phi: float) -> tuple[bool, int]:
+    """(outside the heliopause, parameter region) at a point."""
+    k = ctypes.c_int32()
+    out = lib().orc_locate(ctypes.byref(p), r, theta, phi, ctypes.byref(k))
+    if out < 0:
+        raise ValueError("oracle rejected the parameters")
+    return bool(out), int(k.value)
 
 
 def lis(p: OrcParams, P: float) -> float:

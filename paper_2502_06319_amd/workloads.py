@@ -70,7 +70,55 @@ def helio_1d(kappa0=1.5e22, v=400.0, r_boundary=100.0, dt_max=5e4) -> dict:
         "dt_max_s": float(dt_max),
         "dt_diff_frac": 0.02,
         "dt_adv_frac": 0.0,
+        **SPHERICAL_NO_HELIOSHEATH,
     }
+
+
+# Geometry fields of a spherical heliosphere without a heliosheath: the
+# boundary's nose distance 0 means "equal to r_boundary_au".
+SPHERICAL_NO_HELIOSHEATH = {
+    "r_boundary_nose_au": 0.0,
+    "nose_theta_rad": math.pi / 2,
+    "nose_phi_rad": 0.0,
+    "heliosheath": 0,
+    "ts_nose_au": 0.0,
+    "ts_tail_au": 0.0,
+    "kappa0_hs_cm2_s": 0.0,
+    "v_hs_km_s": 0.0,
+    "tilt_hs_deg": 0.0,
+}
+
+
+def with_heliosheath(helio: dict, ts_nose, ts_tail, hp_nose, hp_tail, kappa0_hs, v_hs,
+                     tilt_hs_deg, nose_theta=math.radians(95.0), nose_phi=0.0) -> dict:
+    """A copy of a 3D heliosphere with a nose-squashed heliopause (distances
+    hp_nose toward the nose, hp_tail toward the tail), a termination shock
+    (ts_nose, ts_tail) and a heliosheath region between them."""
+    h = copy.deepcopy(helio)
+    assert h["model"] == 1
+    h.update({"r_boundary_au": float(hp_tail), "r_boundary_nose_au": float(hp_nose),
+              "nose_theta_rad": float(nose_theta), "nose_phi_rad": float(nose_phi),
+              "heliosheath": 1, "ts_nose_au": float(ts_nose), "ts_tail_au": float(ts_tail),
+              "kappa0_hs_cm2_s": float(kappa0_hs), "v_hs_km_s": float(v_hs),
+              "tilt_hs_deg": float(tilt_hs_deg)})
+    return h
+
+
+def draw_heliosheath(rng: np.random.Generator, helio: dict) -> dict:
+    """Synthetic heliosheath geometry for a drawn parameter set (stand-in for
+    the HelMod geometry, which is not available): termination shock at
+    U[80, 90] AU toward the nose and 1.2-1.4x that toward the tail; heliopause
+    at U[115, 125] AU toward the nose and 1.3-1.5x that toward the tail; nose
+    5 deg south of the solar equator at a uniform longitude from the injection
+    point; heliosheath kappa0 ~ U[0.2, 1.0]e22 cm^2/s, wind U[100, 200] km/s,
+    current-sheet tilt of the outermost shell."""
+    ts_n = rng.uniform(80.0, 90.0)
+    hp_n = rng.uniform(115.0, 125.0)
+    return with_heliosheath(helio, ts_n, ts_n * rng.uniform(1.2, 1.4), hp_n,
+                            hp_n * rng.uniform(1.3, 1.5), rng.uniform(0.2e22, 1.0e22),
+                            rng.uniform(100.0, 200.0), helio["tilt_deg"][-1],
+                            nose_theta=math.radians(95.0),
+                            nose_phi=rng.uniform(0.0, 2.0 * math.pi))
 
 
 def helio_3d(kappa0, v_slow, tilt_deg, polarity=1, r_boundary=120.0, drift=1, hcs=1,
@@ -102,6 +150,7 @@ def helio_3d(kappa0, v_slow, tilt_deg, polarity=1, r_boundary=120.0, drift=1, hc
         "dt_max_s": float(dt_max),
         "dt_diff_frac": 0.02,
         "dt_adv_frac": float(dt_adv_frac),
+        **SPHERICAL_NO_HELIOSHEATH,
     }
 
 
