@@ -31,8 +31,9 @@
 extern "C" {
 #endif
 
-#define COSMICA_ABI_VERSION 1
+#define COSMICA_ABI_VERSION 2
 #define COSMICA_MAX_REGIONS 15 /* radial shells of the inner heliosphere (Sec. II.B) */
+#define COSMICA_REGION_HELIOSHEATH 15 /* region index of the heliosheath */
 #define COSMICA_NHIST 129      /* 128 bins of log10(P_ex/P0) over [0,3) + overflow */
 #define COSMICA_MAX_STEP_CAP 16777215u
 
@@ -59,7 +60,21 @@ typedef enum { COSMICA_PREC_FP64 = 0, COSMICA_PREC_MIXED = 1 } cosmica_precision
  *   it; wind v_slow inside |latitude| <= tilt, v_fast outside; gradient-curvature
  *   drift (drift=1) and a wavy current sheet of the shell's tilt (hcs=1).
  * The inner heliosphere is split into n_regions equal-width shells out to
- * r_boundary_au (Sec. II.B); each shell has its own kappa0, v_slow and tilt. */
+ * r_boundary_au (Sec. II.B); each shell has its own kappa0, v_slow and tilt.
+ * 3D only: the heliosphere can be squashed toward its nose and carry a
+ * heliosheath (Sec. II.B names both regions and the squashing; the shape is
+ * this library's reading).  The heliopause and the termination shock are each
+ * a sphere whose centre sits behind the Sun, against the nose direction
+ * (nose_theta_rad, nose_phi_rad), fixed by its distances from the Sun toward the
+ * nose and toward the tail; r_boundary_au is then the heliopause's tail
+ * distance.  A point is outside a surface with distances Rn, Rt when
+ * r^2 + (Rt - Rn) r cos(psi) >= Rn Rt, psi its angle from the nose.  With a
+ * heliosheath the shells span the inner heliosphere up to the shock's nose
+ * distance, and beyond the shock the heliosheath's own kappa0, wind (one speed,
+ * no fast/slow band) and current-sheet tilt apply.  The shock is a parameter
+ * discontinuity like the shell edges, not a source of acceleration.  With
+ * r_boundary_nose_au = 0 and heliosheath = 0 the heliosphere is the sphere of
+ * radius r_boundary_au. */
 typedef struct {
     int32_t model;           /* cosmica_model */
     int32_t n_regions;       /* 1..15 */
@@ -80,6 +95,14 @@ typedef struct {
     double dt_max_s;         /* > 0 */
     double dt_diff_frac;     /* > 0: dt <= frac r^2 / k_par */
     double dt_adv_frac;      /* >= 0: 3D, dt <= frac r / |A|; 0 disables */
+    double r_boundary_nose_au; /* 0 (spherical), or heliopause toward the nose in (r0, r_boundary_au] */
+    double nose_theta_rad, nose_phi_rad; /* nose direction (colatitude, longitude) */
+    int32_t heliosheath;     /* 0 or 1 (3D only) */
+    int32_t reserved1;
+    double ts_nose_au, ts_tail_au; /* termination shock: r0 < ts_nose <= ts_tail */
+    double kappa0_hs_cm2_s;  /* heliosheath kappa0, > 0 */
+    double v_hs_km_s;        /* heliosheath wind, >= 0 (> 0 when drift) */
+    double tilt_hs_deg;      /* heliosheath current-sheet tilt, [0, 90) */
 } cosmica_helio;
 
 /* Particle species: rigidity P = pc/(|Z| e) [GV] (Sec. VI); LIS J(P) = lis_norm P^-lis_index. */
@@ -288,6 +311,14 @@ cosmica_status cosmica_probe_rng(cosmica_ctx* ctx, uint64_t seed, uint32_t c0, u
 cosmica_status cosmica_probe_coeffs(cosmica_ctx* ctx, const cosmica_job* job,
                                     cosmica_precision precision, uint32_t n, const double* pts,
                                     double* out);
+/* cosmica_probe_locate: where n points pts[3i..3i+2] = (r [AU], theta, phi)
+ *   lie for job->helio (Sec. II.B regions), decided by the integrator's own
+ *   device code in the given precision: region[i] = the parameter region (0..
+ *   n_regions-1 the shells, 15 the heliosheath), outside[i] = 1 if the point is
+ *   beyond the heliopause (the exit test), else 0.  Host buffers. */
+cosmica_status cosmica_probe_locate(cosmica_ctx* ctx, const cosmica_job* job,
+                                    cosmica_precision precision, uint32_t n, const double* pts,
+                                    int32_t* region, int32_t* outside);
 
 #ifdef __cplusplus
 }

@@ -46,7 +46,18 @@ class Helio(ctypes.Structure):
         ("reserved0", ctypes.c_int32),
         ("dt_max_s", ctypes.c_double), ("dt_diff_frac", ctypes.c_double),
         ("dt_adv_frac", ctypes.c_double),
+        ("r_boundary_nose_au", ctypes.c_double), ("nose_theta_rad", ctypes.c_double),
+        ("nose_phi_rad", ctypes.c_double), ("heliosheath", ctypes.c_int32),
+        ("reserved1", ctypes.c_int32), ("ts_nose_au", ctypes.c_double),
+        ("ts_tail_au", ctypes.c_double), ("kappa0_hs_cm2_s", ctypes.c_double),
+        ("v_hs_km_s", ctypes.c_double), ("tilt_hs_deg", ctypes.c_double),
     ]
+
+# geometry fields that older job dictionaries may lack: a spherical heliosphere
+_HELIO_DEFAULTS = {"r_boundary_nose_au": 0.0, "nose_theta_rad": 0.5 * np.pi, "nose_phi_rad": 0.0,
+                   "heliosheath": 0, "ts_nose_au": 0.0, "ts_tail_au": 0.0,
+                   "kappa0_hs_cm2_s": 0.0, "v_hs_km_s": 0.0, "tilt_hs_deg": 0.0}
+REGION_HELIOSHEATH = 15
 
 
 class Species(ctypes.Structure):
@@ -139,6 +150,10 @@ _SIGS = {
                                          ctypes.POINTER(ctypes.c_float)]),
     "cosmica_probe_coeffs": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Job), ctypes.c_int,
                                             ctypes.c_uint32, c_double_p, c_double_p]),
+    "cosmica_probe_locate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Job), ctypes.c_int,
+                                            ctypes.c_uint32, c_double_p,
+                                            ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32)]),
 }
 
 _lib = None
@@ -180,9 +195,9 @@ class _JobPack:
         sp = job["species"]
         self.helio = Helio()
         for name, ctype in Helio._fields_:
-            if name == "reserved0":
+            if name in ("reserved0", "reserved1"):
                 continue
-            v = h[name]
+            v = h[name] if name in h else _HELIO_DEFAULTS[name]
             if name in ("kappa0_cm2_s", "v_slow_km_s", "tilt_deg"):
                 arr = getattr(self.helio, name)
                 for k, x in enumerate(v):
@@ -420,6 +435,20 @@ class Engine:
                                            len(pts), pts.ctypes.data_as(c_double_p),
                                            out.ctypes.data_as(c_double_p)), "probe_coeffs")
         return out
+
+
+    def probe_locate(self, job: dict, pts, precision="fp64"):
+        """(region, outside) at points (r, theta, phi), decided on the device."""
+        p = _JobPack(job)
+        pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+        region = np.zeros(len(pts), dtype=np.int32)
+        outside = np.zeros(len(pts), dtype=np.int32)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        _check(load().cosmica_probe_locate(self.handle, ctypes.byref(p.job), PRECISION[precision],
+                                           len(pts), pts.ctypes.data_as(c_double_p),
+                                           region.ctypes.data_as(i32p),
+                                           outside.ctypes.data_as(i32p)), "probe_locate")
+        return region, outside.astype(bool)
 
 
 PROBE_FIELDS = ("Ar", "At", "Ap", "AP", "Brr", "Bpr", "Bpp", "Btt", "dt", "Hw", "vdr", "vdt",

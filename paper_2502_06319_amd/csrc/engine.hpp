@@ -13,6 +13,7 @@ namespace cosmica {
 
 constexpr int kMaxRegions = 15;
 constexpr int kRegionStride = 16;  // region-table entries reserved per job
+constexpr int kRegionHeliosheath = 15;  // the heliosheath's entry
 constexpr int kNHist = 129;
 constexpr uint32_t kFlagCapped = 1u;
 constexpr uint32_t kFlagNaN = 2u;
@@ -24,10 +25,17 @@ constexpr int kFlagShift = 24;  // exit word = n | flags << 24 (n < 2^24)
 template <typename R>
 struct alignas(16) JobDev {
     uint32_t seed_lo, seed_hi, job_tag, step_cap;
-    int32_t nreg, drift, hcs, pad0;
-    double rb;         // absorbing boundary [AU]
-    double inv_shell;  // n_regions / rb [1/AU]
-    double r0, th0, ph0, pad1;
+    int32_t nreg, drift, hcs, shaped;  // shaped: nose-squashed boundary or heliosheath
+    double rb;         // heliopause nose distance: every r >= rb may be outside [AU]
+    double inv_shell;  // n_regions / (extent of the shells) [1/AU]
+    double r0, th0, ph0;
+    double rb_tail;    // heliopause tail distance: every r >= rb_tail is outside
+    // Surfaces with nose / tail distances Rn, Rt: outside when
+    // r^2 + (Rt - Rn) r cos(psi) >= Rn Rt (psi: angle from the nose).
+    double hp_d2, hp_prod;       // heliopause: Rt - Rn, Rn Rt
+    double ts_nose, ts_tail;     // termination shock (ts_nose = +inf: no heliosheath)
+    double ts_d2, ts_prod;
+    R sin_tn, cos_tn, ph_n, pad_n;  // nose direction: sin, cos of its colatitude; longitude
     R vf;          // fast wind [AU/s]
     R omega;       // solar rotation [rad/s]
     R kperp_frac;  // f = kappa_perp / kappa_par
@@ -41,11 +49,12 @@ struct alignas(16) JobDev {
     R dt_max, diff_frac, adv_frac;
 };
 
-// One radial shell: kappa0 [AU^2/s], slow wind [AU/s], tilt [rad], tan(tilt),
-// omega / slow wind [rad/AU].
+// One parameter region (a radial shell, or the heliosheath): kappa0 [AU^2/s],
+// slow wind [AU/s], tilt [rad], tan(tilt), omega / slow wind [rad/AU], fast
+// wind [AU/s].
 template <typename R>
 struct alignas(16) RegionDev {
-    R k0, vs, alpha, tana, om_vs, pad0, pad1, pad2;
+    R k0, vs, alpha, tana, om_vs, vf, pad1, pad2;
 };
 
 // One (job, rigidity bin) segment of the flat work index.
@@ -93,6 +102,7 @@ struct PropArgs {
     uint32_t* suspend_count;      // zeroed before launch
     uint32_t step_budget;         // steps per wave per launch (0xffffffff: unlimited)
     uint32_t uniform_key;         // 1: every job of the launch has the Philox key below
+    uint32_t shaped;              // 1: some job of the launch has a squashed boundary or a heliosheath
     uint32_t key_lo, key_hi;
     const uint32_t* job_cancel;   // optional per-job cancel flags
     uint32_t* job_done;           // optional per-job count of finished particles
@@ -122,7 +132,7 @@ hipError_t launch_propagate_3d_mixed(const PropArgs<float>& a, int grid, int blo
 hipError_t launch_propagate_3d_fp64(const PropArgs<double>& a, int grid, int block, hipStream_t s);
 hipError_t launch_propagate_1d_mixed(const PropArgs<float>& a, int grid, int block, hipStream_t s);
 hipError_t launch_propagate_1d_fp64(const PropArgs<double>& a, int grid, int block, hipStream_t s);
-hipError_t occupancy_propagate(int model, int prec, int block, int* blocks_per_cu);
+hipError_t occupancy_propagate(int model, int prec, int block, int shaped, int* blocks_per_cu);
 hipError_t launch_reduce(const ReduceArgs& a, uint32_t n_segs, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint32_t n, hipStream_t s);
 
@@ -136,5 +146,11 @@ hipError_t launch_probe_coeffs_fp64(const JobDev<double>* job, const RegionDev<d
 hipError_t launch_probe_coeffs_mixed(const JobDev<float>* job, const RegionDev<float>* reg,
                                      const double* pts, uint32_t n, double* out, hipStream_t s);
 constexpr int kProbeOut = 16;
+hipError_t launch_probe_locate_fp64(const JobDev<double>* job, const RegionDev<double>* reg,
+                                    const double* pts, uint32_t n, int32_t* region,
+                                    int32_t* outside, hipStream_t s);
+hipError_t launch_probe_locate_mixed(const JobDev<float>* job, const RegionDev<float>* reg,
+                                     const double* pts, uint32_t n, int32_t* region,
+                                     int32_t* outside, hipStream_t s);
 
 }  // namespace cosmica

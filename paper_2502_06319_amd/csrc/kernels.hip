@@ -82,6 +82,10 @@ struct Mth<float> {
     {
         sincos_rev(x * 0.159154943091895336f, s, c);
     }
+    static __device__ __forceinline__ float cos_rad(float x)
+    {
+        return __builtin_amdgcn_cosf(x * 0.159154943091895336f);
+    }
     static __device__ __forceinline__ float atan(float x) { return ::atanf(x); }
     static __device__ __forceinline__ float tanh(float x)
     {
@@ -107,6 +111,7 @@ struct Mth<double> {
     {
         ::sincos(x, s, c);
     }
+    static __device__ __forceinline__ double cos_rad(double x) { return ::cos(x); }
     static __device__ __forceinline__ double atan(double x) { return ::atan(x); }
     static __device__ __forceinline__ double tanh(double x) { return ::tanh(x); }
     static __device__ __forceinline__ double fmod2pi(double x) { return ::fmod(x, kTwoPi); }
@@ -186,9 +191,10 @@ struct Coef3 {
 // many jobs the lanes of a wave belong to.
 template <typename R>
 struct JobReg {
-    R vf, omega, kfrac, omf, sqf2, twof, gcoef, hb, abs_z, mass2, sqA, dt_max, diff_frac,
+    R omega, kfrac, omf, sqf2, twof, gcoef, hb, abs_z, mass2, sqA, dt_max, diff_frac,
         adv_frac;
     double rb, inv_shell;
+    double rb_tail, ts_nose, ts_tail;  // used by the kernels of squashed heliospheres
     uint32_t seed_lo, seed_hi, job_tag, step_cap;
     int32_t nreg, drift, hcs;
 };
@@ -197,7 +203,6 @@ template <typename R>
 __device__ __forceinline__ JobReg<R> load_job(const JobDev<R>& J)
 {
     JobReg<R> o;
-    o.vf = J.vf;
     o.omega = J.omega;
     o.kfrac = J.kperp_frac;
     o.omf = J.omf;
@@ -213,6 +218,9 @@ __device__ __forceinline__ JobReg<R> load_job(const JobDev<R>& J)
     o.adv_frac = J.adv_frac;
     o.rb = J.rb;
     o.inv_shell = J.inv_shell;
+    o.rb_tail = J.rb_tail;
+    o.ts_nose = J.ts_nose;
+    o.ts_tail = J.ts_tail;
     o.seed_lo = J.seed_lo;
     o.seed_hi = J.seed_hi;
     o.job_tag = J.job_tag;
@@ -229,6 +237,49 @@ __device__ __forceinline__ int region_of(const JobReg<R>& J, double r)
 {
     const int k = (int)(r * J.inv_shell);
     return k < J.nreg - 1 ? k : J.nreg - 1;
+}
+
+// Side of a heliospheric surface with distances Rn toward the nose and Rt
+// toward the tail (Sec. II.B squashing; the sphere of radius (Rn + Rt)/2
+// centred (Rt - Rn)/2 behind the Sun): outside when
+// r^2 + (Rt - Rn) r cos(psi) >= Rn Rt, psi the angle from the nose.  Called
+// only for Rn <= r < Rt, where the answer depends on the direction.
+template <typename R>
+__device__ __forceinline__ bool outside_surface(const JobDev<R>& G, double d2, double prod,
+                                                double r, R th, R ph)
+{
+    using M = Mth<R>;
+    R st, ct;
+    M::sincos_rad(th, &st, &ct);
+    const R cpsi = st * G.sin_tn * M::cos_rad(ph - G.ph_n) + ct * G.cos_tn;
+    return r * r + (d2 * r) * (double)cpsi >= prod;
+}
+
+// Parameter region at a point: the heliosheath beyond the termination shock,
+// else the shell of r.  Without SHAPED the heliosphere is a sphere with no
+// heliosheath.  jd: the lane's job entry, read only near the shock.
+template <typename R, bool SHAPED>
+__device__ __forceinline__ int region_at(const JobReg<R>& J, const JobDev<R>* __restrict__ jd,
+                                         double r, R th, R ph)
+{
+    int k = region_of(J, r);
+    if (SHAPED && r >= J.ts_nose) {
+        if (r >= J.ts_tail || outside_surface(*jd, jd->ts_d2, jd->ts_prod, r, th, ph))
+            k = kRegionHeliosheath;
+    }
+    return k;
+}
+
+// Exit test: beyond the heliopause.  A NaN r counts as outside, so a
+// non-finite particle also leaves the step loop.
+template <typename R, bool SHAPED>
+__device__ __forceinline__ bool outside_boundary(const JobReg<R>& J,
+                                                 const JobDev<R>* __restrict__ jd, double r,
+                                                 R th, R ph)
+{
+    bool out = !(r < J.rb);
+    if (SHAPED && out && r < J.rb_tail) out = outside_surface(*jd, jd->hp_d2, jd->hp_prod, r, th, ph);
+    return out;
 }
 
 // Local coefficients, written to share every common factor:
@@ -252,7 +303,7 @@ __device__ __forceinline__ void coeffs3d(const JobReg<R>& J, const RegionDev<R>&
     const R irs = invr * invst;
     // wind: slow inside |latitude| <= tilt of the shell, fast outside
     const R lam = (R)(0.5 * kPi) - th;
-    const R V = (fabs(lam) <= g.alpha) ? g.vs : J.vf;
+    const R V = (fabs(lam) <= g.alpha) ? g.vs : g.vf;
     // diffusion tensor: k_par along b ~ (1, 0, -Gamma), k_perp across
     const R pc = J.abs_z * P;
     const R beta = pc * M::rsqrt(pc * pc + J.mass2);
@@ -349,16 +400,16 @@ __device__ __forceinline__ void coeffs3d(const JobReg<R>& J, const RegionDev<R>&
     }
 }
 
-// One EM step of the 3D model.  The caller tests r >= rb.
-template <typename R, bool UKEY>
-__device__ __forceinline__ void step3d(const JobReg<R>& J, const RegionDev<R>* __restrict__ reg,
-                                       PState<R>& s, uint32_t pid, uint32_t bin, uint32_t k0,
-                                       uint32_t k1)
+// One EM step of the 3D model.  The caller tests for the exit.
+template <typename R, bool UKEY, bool SHAPED>
+__device__ __forceinline__ void step3d(const JobReg<R>& J, const JobDev<R>* __restrict__ jd,
+                                       const RegionDev<R>* __restrict__ reg, PState<R>& s,
+                                       uint32_t pid, uint32_t bin, uint32_t k0, uint32_t k1)
 {
     using M = Mth<R>;
     R z[3];
     normals<R, 3>(UKEY ? k0 : J.seed_lo, UKEY ? k1 : J.seed_hi, s.n, pid, bin, J.job_tag, z);
-    const RegionDev<R> g = reg[region_of(J, s.r)];
+    const RegionDev<R> g = reg[region_at<R, SHAPED>(J, jd, s.r, s.th, s.ph)];
     Coef3<R> c;
     coeffs3d<R, false>(J, g, s.r, s.P, s.th, s.ph, c);
     const R dt = c.dt;
@@ -456,7 +507,7 @@ __device__ __forceinline__ uint32_t wave_uniform(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
-template <typename R, bool M3D, bool UKEY>
+template <typename R, bool M3D, bool UKEY, bool SHAPED>
 __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
 {
     const uint32_t lane = __lane_id();
@@ -464,6 +515,7 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
     uint32_t pid = 0, bin = 0, job = 0, out = 0, seg = 0;
     JobReg<R> J = {};
     const RegionDev<R>* reg = a.regions;
+    const JobDev<R>* jd = a.jobs;  // the lane's job entry (surface constants)
     bool active = false;
     // steps this wave has taken in this launch (wave-uniform), counted against
     // a.step_budget when the launch is a slice
@@ -504,6 +556,7 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
                 bin = sg.bin;
                 out = sg.out_offset + pid;
                 J = load_job(a.jobs[job]);
+                jd = a.jobs + job;
                 reg = a.regions + (size_t)job * kRegionStride;
                 active = true;
             }
@@ -535,6 +588,7 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
                 bin = sg.bin;
                 out = sg.out_offset + pid;
                 J = load_job(Jd);
+                jd = a.jobs + job;
                 reg = a.regions + (size_t)job * kRegionStride;
                 s.r = Jd.r0;
                 s.th = (R)Jd.th0;
@@ -574,20 +628,21 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
             bool leave = false;
             if (active) {
                 if (M3D)
-                    step3d<R, UKEY>(J, reg, s, pid, bin, a.key_lo, a.key_hi);
+                    step3d<R, UKEY, SHAPED>(J, jd, reg, s, pid, bin, a.key_lo, a.key_hi);
                 else
                     step1d<R, UKEY>(J, reg, s, pid, bin, a.key_lo, a.key_hi);
-                // !(r < rb) also holds for a NaN r
-                leave = !(s.r < J.rb) || !(s.P == s.P) || s.n >= J.step_cap;
+                leave = outside_boundary<R, SHAPED>(J, jd, s.r, s.th, s.ph) || !(s.P == s.P) ||
+                        s.n >= J.step_cap;
             }
             ++wave_steps;
             if (__any(leave) || (sliced && wave_steps >= a.step_budget)) break;
         }
-        if (active && (!(s.r < J.rb) || !(s.P == s.P) || s.n >= J.step_cap)) {
+        const bool outside = active && outside_boundary<R, SHAPED>(J, jd, s.r, s.th, s.ph);
+        if (active && (outside || !(s.P == s.P) || s.n >= J.step_cap)) {
             uint32_t flags = 0;
             if (!(s.r == s.r) || !(s.P == s.P))
                 flags = kFlagNaN;
-            else if (!(s.r >= J.rb))
+            else if (!outside)
                 flags = kFlagCapped;
             a.exP[out] = s.P;
             a.exT[out] = s.t;
@@ -623,14 +678,27 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
     }
 }
 
-template <typename R, bool M3D>
-static hipError_t launch_prop(const PropArgs<R>& a, int grid, int block, hipStream_t s)
+template <typename R, bool M3D, bool SHAPED>
+static void launch_keyed(const PropArgs<R>& a, int grid, int block, hipStream_t s)
 {
     // one Philox key for the whole launch: the key schedule runs on the scalar unit
     if (a.uniform_key)
-        hipLaunchKernelGGL((k_propagate<R, M3D, true>), dim3(grid), dim3(block), 0, s, a);
+        hipLaunchKernelGGL((k_propagate<R, M3D, true, SHAPED>), dim3(grid), dim3(block), 0, s, a);
     else
-        hipLaunchKernelGGL((k_propagate<R, M3D, false>), dim3(grid), dim3(block), 0, s, a);
+        hipLaunchKernelGGL((k_propagate<R, M3D, false, SHAPED>), dim3(grid), dim3(block), 0, s, a);
+}
+
+template <typename R, bool M3D>
+static hipError_t launch_prop(const PropArgs<R>& a, int grid, int block, hipStream_t s)
+{
+    // squashed heliopause / heliosheath tests only where a job of the launch has them
+    if constexpr (M3D) {
+        if (a.shaped) {
+            launch_keyed<R, M3D, true>(a, grid, block, s);
+            return hipGetLastError();
+        }
+    }
+    launch_keyed<R, M3D, false>(a, grid, block, s);
     return hipGetLastError();
 }
 
@@ -651,21 +719,27 @@ hipError_t launch_propagate_1d_fp64(const PropArgs<double>& a, int grid, int blo
     return launch_prop<double, false>(a, grid, block, s);
 }
 
-hipError_t occupancy_propagate(int model, int prec, int block, int* blocks_per_cu)
+hipError_t occupancy_propagate(int model, int prec, int block, int shaped, int* blocks_per_cu)
 {
     const void* f[2] = {nullptr, nullptr};
-    if (model == 1 && prec == 1) {
-        f[0] = (const void*)&k_propagate<float, true, false>;
-        f[1] = (const void*)&k_propagate<float, true, true>;
+    if (model == 1 && prec == 1 && shaped) {
+        f[0] = (const void*)&k_propagate<float, true, false, true>;
+        f[1] = (const void*)&k_propagate<float, true, true, true>;
+    } else if (model == 1 && prec == 1) {
+        f[0] = (const void*)&k_propagate<float, true, false, false>;
+        f[1] = (const void*)&k_propagate<float, true, true, false>;
+    } else if (model == 1 && prec == 0 && shaped) {
+        f[0] = (const void*)&k_propagate<double, true, false, true>;
+        f[1] = (const void*)&k_propagate<double, true, true, true>;
     } else if (model == 1 && prec == 0) {
-        f[0] = (const void*)&k_propagate<double, true, false>;
-        f[1] = (const void*)&k_propagate<double, true, true>;
+        f[0] = (const void*)&k_propagate<double, true, false, false>;
+        f[1] = (const void*)&k_propagate<double, true, true, false>;
     } else if (model == 0 && prec == 1) {
-        f[0] = (const void*)&k_propagate<float, false, false>;
-        f[1] = (const void*)&k_propagate<float, false, true>;
+        f[0] = (const void*)&k_propagate<float, false, false, false>;
+        f[1] = (const void*)&k_propagate<float, false, true, false>;
     } else if (model == 0 && prec == 0) {
-        f[0] = (const void*)&k_propagate<double, false, false>;
-        f[1] = (const void*)&k_propagate<double, false, true>;
+        f[0] = (const void*)&k_propagate<double, false, false, false>;
+        f[1] = (const void*)&k_propagate<double, false, true, false>;
     } else {
         return hipErrorInvalidValue;
     }
@@ -847,7 +921,7 @@ __global__ void k_probe_coeffs(const JobDev<R>* job, const RegionDev<R>* reg, co
     const double P = pts[4 * (size_t)i + 0], r = pts[4 * (size_t)i + 1];
     const R th = (R)pts[4 * (size_t)i + 2], ph = (R)pts[4 * (size_t)i + 3];
     Coef3<R> c;
-    coeffs3d<R, true>(J, reg[region_of(J, r)], r, P, th, ph, c);
+    coeffs3d<R, true>(J, reg[region_at<R, true>(J, job, r, th, ph)], r, P, th, ph, c);
     double* o = out + (size_t)kProbeOut * i;
     o[0] = c.Ar;
     o[1] = c.At;
@@ -882,6 +956,41 @@ hipError_t launch_probe_coeffs_mixed(const JobDev<float>* job, const RegionDev<f
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_probe_coeffs<float>, dim3((n + 63) / 64), dim3(64), 0, s, job, reg, pts,
                        n, out);
+    return hipGetLastError();
+}
+
+// Region and exit decision at points (r, theta, phi), with the integrator's
+// own device functions.
+template <typename R>
+__global__ void k_probe_locate(const JobDev<R>* job, const double* pts, uint32_t n,
+                               int32_t* region, int32_t* outside)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const JobReg<R> J = load_job(*job);
+    const double r = pts[3 * (size_t)i + 0];
+    const R th = (R)pts[3 * (size_t)i + 1], ph = (R)pts[3 * (size_t)i + 2];
+    region[i] = region_at<R, true>(J, job, r, th, ph);
+    outside[i] = outside_boundary<R, true>(J, job, r, th, ph) ? 1 : 0;
+}
+
+hipError_t launch_probe_locate_fp64(const JobDev<double>* job, const RegionDev<double>*,
+                                    const double* pts, uint32_t n, int32_t* region,
+                                    int32_t* outside, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe_locate<double>, dim3((n + 63) / 64), dim3(64), 0, s, job, pts, n,
+                       region, outside);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_locate_mixed(const JobDev<float>* job, const RegionDev<float>*,
+                                     const double* pts, uint32_t n, int32_t* region,
+                                     int32_t* outside, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe_locate<float>, dim3((n + 63) / 64), dim3(64), 0, s, job, pts, n,
+                       region, outside);
     return hipGetLastError();
 }
 

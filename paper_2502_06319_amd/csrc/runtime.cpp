@@ -97,6 +97,26 @@ cosmica_status validate(const cosmica_job* j)
         if (!std::isfinite(h.tilt_deg[k]) || h.tilt_deg[k] < 0.0 || !(h.tilt_deg[k] < 90.0))
             return COSMICA_EINVAL;
     }
+    // nose-squashed heliopause and heliosheath (3D only)
+    const bool nosed = h.r_boundary_nose_au != 0.0;
+    if (h.heliosheath != 0 && h.heliosheath != 1) return COSMICA_EINVAL;
+    if ((nosed || h.heliosheath == 1) && h.model != COSMICA_MODEL_3D) return COSMICA_EINVAL;
+    if (nosed && (!finite_pos(h.r_boundary_nose_au) || !(h.r_boundary_nose_au <= h.r_boundary_au) ||
+                  !(h.r0_au < h.r_boundary_nose_au)))
+        return COSMICA_EINVAL;
+    if ((nosed || h.heliosheath == 1) &&
+        (!std::isfinite(h.nose_theta_rad) || !std::isfinite(h.nose_phi_rad)))
+        return COSMICA_EINVAL;
+    if (h.heliosheath == 1) {
+        if (!finite_pos(h.ts_nose_au) || !std::isfinite(h.ts_tail_au) || !(h.r0_au < h.ts_nose_au) ||
+            !(h.ts_nose_au <= h.ts_tail_au))
+            return COSMICA_EINVAL;
+        if (!finite_pos(h.kappa0_hs_cm2_s)) return COSMICA_EINVAL;
+        if (!std::isfinite(h.v_hs_km_s) || h.v_hs_km_s < 0.0) return COSMICA_EINVAL;
+        if (drift && !(h.v_hs_km_s > 0.0)) return COSMICA_EINVAL;
+        if (!std::isfinite(h.tilt_hs_deg) || h.tilt_hs_deg < 0.0 || !(h.tilt_hs_deg < 90.0))
+            return COSMICA_EINVAL;
+    }
     if (h.model == COSMICA_MODEL_3D) {
         if (!std::isfinite(h.v_fast_km_s) || h.v_fast_km_s < 0.0) return COSMICA_EINVAL;
         if (drift && !(h.v_fast_km_s > 0.0)) return COSMICA_EINVAL;
@@ -118,6 +138,15 @@ cosmica_status validate(const cosmica_job* j)
     if (total >= (1ull << 32)) return COSMICA_EINVAL;
     if ((uint64_t)j->bin_offset + (uint64_t)j->n_bins > (1ull << 32)) return COSMICA_EINVAL;
     return COSMICA_OK;
+}
+
+// A job whose heliopause is squashed or that has a heliosheath needs the
+// propagation kernel that tests those surfaces.
+bool job_shaped(const JobCopy& jc)
+{
+    const cosmica_helio& h = jc.helio;
+    return h.model == COSMICA_MODEL_3D &&
+           (h.heliosheath == 1 || (h.r_boundary_nose_au > 0.0 && h.r_boundary_nose_au != h.r_boundary_au));
 }
 
 JobCopy copy_job(const cosmica_job* j)
@@ -149,8 +178,26 @@ void make_tables(const JobCopy& jc, JobDev<R>* J, RegionDev<R>* reg, LisDev* lis
     J->nreg = h.n_regions;
     J->drift = h.model == COSMICA_MODEL_3D ? h.drift : 0;
     J->hcs = h.model == COSMICA_MODEL_3D ? h.hcs : 0;
-    J->rb = h.r_boundary_au;
-    J->inv_shell = (double)h.n_regions / h.r_boundary_au;
+    // heliopause: nose and tail distances (equal for a sphere); termination
+    // shock only with a heliosheath
+    const bool hs = h.model == COSMICA_MODEL_3D && h.heliosheath == 1;
+    const double rb_nose = h.r_boundary_nose_au > 0.0 ? h.r_boundary_nose_au : h.r_boundary_au;
+    J->rb = rb_nose;
+    J->rb_tail = h.r_boundary_au;
+    J->hp_d2 = h.r_boundary_au - rb_nose;
+    J->hp_prod = rb_nose * h.r_boundary_au;
+    J->ts_nose = hs ? h.ts_nose_au : HUGE_VAL;
+    J->ts_tail = hs ? h.ts_tail_au : HUGE_VAL;
+    J->ts_d2 = hs ? h.ts_tail_au - h.ts_nose_au : 0.0;
+    J->ts_prod = hs ? h.ts_nose_au * h.ts_tail_au : 0.0;
+    J->shaped = (hs || rb_nose != h.r_boundary_au) ? 1 : 0;
+    J->sin_tn = (R)std::sin(h.nose_theta_rad);
+    J->cos_tn = (R)std::cos(h.nose_theta_rad);
+    const double phn = std::fmod(h.nose_phi_rad, 2.0 * kPiH);
+    J->ph_n = (R)(phn < 0.0 ? phn + 2.0 * kPiH : phn);
+    // the shells split the inner heliosphere up to the shock's (or else the
+    // heliopause's) nose distance
+    J->inv_shell = (double)h.n_regions / (hs ? h.ts_nose_au : rb_nose);
     J->r0 = h.r0_au;
     J->th0 = h.theta0_rad;
     J->ph0 = h.phi0_rad;
@@ -181,10 +228,15 @@ void make_tables(const JobCopy& jc, JobDev<R>* J, RegionDev<R>* reg, LisDev* lis
         RegionDev<R>& g = reg[k];
         std::memset(&g, 0, sizeof(g));
         const int kk = k < h.n_regions ? k : h.n_regions - 1;
-        const double vs = h.v_slow_km_s[kk] / kAuKm;
-        const double alpha = h.tilt_deg[kk] * kPiH / 180.0;
-        g.k0 = (R)(h.kappa0_cm2_s[kk] / (kAuCm * kAuCm));
+        const bool sheath = hs && k == kRegionHeliosheath;
+        // the heliosheath has one wind speed for both bands
+        const double vs = (sheath ? h.v_hs_km_s : h.v_slow_km_s[kk]) / kAuKm;
+        const double vf = (sheath ? h.v_hs_km_s : h.v_fast_km_s) / kAuKm;
+        const double alpha = (sheath ? h.tilt_hs_deg : h.tilt_deg[kk]) * kPiH / 180.0;
+        const double k0 = sheath ? h.kappa0_hs_cm2_s : h.kappa0_cm2_s[kk];
+        g.k0 = (R)(k0 / (kAuCm * kAuCm));
         g.vs = (R)vs;
+        g.vf = (R)vf;
         g.alpha = (R)alpha;
         g.tana = (R)std::tan(alpha);
         g.om_vs = vs > 0.0 ? (R)(h.omega_rad_s / vs) : (R)0;
@@ -307,10 +359,12 @@ void make_chunks(const std::vector<SegmentDev>& segs, const std::vector<uint32_t
     }
 }
 
-int grid_for(cosmica_ctx* ctx, int model, int prec, const cosmica_launch& L, uint64_t lanes_wanted)
+int grid_for(cosmica_ctx* ctx, int model, int prec, const cosmica_launch& L, uint64_t lanes_wanted,
+             bool shaped)
 {
     int occ = 0;
-    if (occupancy_propagate(model, prec, L.block, &occ) != hipSuccess || occ < 1) occ = 1;
+    if (occupancy_propagate(model, prec, L.block, shaped ? 1 : 0, &occ) != hipSuccess || occ < 1)
+        occ = 1;
     int bpc = L.blocks_per_cu > 0 ? std::min(L.blocks_per_cu, occ) : occ;
     uint64_t grid = (uint64_t)ctx->num_cus * (uint64_t)bpc;
     const uint64_t need = (lanes_wanted + (uint64_t)L.block - 1) / (uint64_t)L.block;
@@ -381,6 +435,7 @@ struct cosmica_plan {
     bool executed = false;
     bool own_out = true;
     bool uniform_key = false;  // every job has the same seed
+    bool shaped = false;       // some job has a squashed heliopause or a heliosheath
     uint64_t key = 0;
     explicit cosmica_plan(cosmica_ctx* c) : ctx(c), mem(c) {}
 };
@@ -446,9 +501,10 @@ cosmica_status execute_prop(cosmica_plan* p)
         a.leftover = nullptr;
         a.leftover_count = p->counters_d + 4;
         a.uniform_key = p->uniform_key ? 1u : 0u;
+        a.shaped = p->shaped ? 1u : 0u;
         a.key_lo = (uint32_t)(p->key & 0xffffffffu);
         a.key_hi = (uint32_t)(p->key >> 32);
-        const int grid = grid_for(ctx, model, p->prec, L, p->model_particles[model]);
+        const int grid = grid_for(ctx, model, p->prec, L, p->model_particles[model], p->shaped);
         ctx->timings.grid_blocks = grid;
         ctx->timings.block = L.block;
         HIP_TRY(launch_model<R>(model, a, grid, L.block, ctx->stream));
@@ -559,6 +615,7 @@ cosmica_status cosmica_plan_create(cosmica_ctx* ctx, const cosmica_job* jobs, in
     p->key = p->jobs[0].seed;
     p->uniform_key = true;
     for (const JobCopy& jc : p->jobs) p->uniform_key &= jc.seed == p->key;
+    for (const JobCopy& jc : p->jobs) p->shaped |= job_shaped(jc);
     cosmica_status st = precision == COSMICA_PREC_MIXED ? upload_tables<float>(p.get())
                                                          : upload_tables<double>(p.get());
     if (st != COSMICA_OK) return st;
@@ -894,6 +951,61 @@ cosmica_status cosmica_probe_coeffs(cosmica_ctx* ctx, const cosmica_job* job,
     return COSMICA_OK;
 }
 
+cosmica_status cosmica_probe_locate(cosmica_ctx* ctx, const cosmica_job* job,
+                                    cosmica_precision precision, uint32_t n, const double* pts,
+                                    int32_t* region, int32_t* outside)
+{
+    if (ctx == nullptr || pts == nullptr || region == nullptr || outside == nullptr || n == 0)
+        return COSMICA_EINVAL;
+    if (validate(job) != COSMICA_OK || job->helio->model != COSMICA_MODEL_3D) return COSMICA_EINVAL;
+    if (precision != COSMICA_PREC_FP64 && precision != COSMICA_PREC_MIXED) return COSMICA_EINVAL;
+    for (uint32_t i = 0; i < n; ++i) {
+        const double* q = pts + 3 * (size_t)i;
+        if (!(q[0] >= 0.0) || !std::isfinite(q[0]) || !(q[1] >= 0.0) || !(q[1] <= kPiH) ||
+            !(q[2] >= 0.0) || !(q[2] < 2.0 * kPiH))
+            return COSMICA_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    const JobCopy jc = copy_job(job);
+    DevSet m(ctx);
+    double* pd = nullptr;
+    int32_t* rd_out = nullptr;
+    int32_t* od = nullptr;
+    cosmica_status st;
+    if ((st = m.alloc(&pd, 3 * (size_t)n)) != COSMICA_OK) return st;
+    if ((st = m.alloc(&rd_out, n)) != COSMICA_OK) return st;
+    if ((st = m.alloc(&od, n)) != COSMICA_OK) return st;
+    HIP_TRY(hipMemcpy(pd, pts, 24 * (size_t)n, hipMemcpyHostToDevice));
+    LisDev lis;
+    if (precision == COSMICA_PREC_FP64) {
+        JobDev<double> J;
+        std::vector<RegionDev<double>> R(kRegionStride);
+        make_tables<double>(jc, &J, R.data(), &lis);
+        JobDev<double>* jd = nullptr;
+        RegionDev<double>* rg = nullptr;
+        if ((st = m.alloc(&jd, 1)) != COSMICA_OK) return st;
+        if ((st = m.alloc(&rg, kRegionStride)) != COSMICA_OK) return st;
+        HIP_TRY(hipMemcpy(jd, &J, sizeof(J), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(rg, R.data(), R.size() * sizeof(R[0]), hipMemcpyHostToDevice));
+        HIP_TRY(launch_probe_locate_fp64(jd, rg, pd, n, rd_out, od, ctx->stream));
+    } else {
+        JobDev<float> J;
+        std::vector<RegionDev<float>> R(kRegionStride);
+        make_tables<float>(jc, &J, R.data(), &lis);
+        JobDev<float>* jd = nullptr;
+        RegionDev<float>* rg = nullptr;
+        if ((st = m.alloc(&jd, 1)) != COSMICA_OK) return st;
+        if ((st = m.alloc(&rg, kRegionStride)) != COSMICA_OK) return st;
+        HIP_TRY(hipMemcpy(jd, &J, sizeof(J), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(rg, R.data(), R.size() * sizeof(R[0]), hipMemcpyHostToDevice));
+        HIP_TRY(launch_probe_locate_mixed(jd, rg, pd, n, rd_out, od, ctx->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipMemcpy(region, rd_out, 4 * (size_t)n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(outside, od, 4 * (size_t)n, hipMemcpyDeviceToHost));
+    return COSMICA_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
@@ -1053,7 +1165,12 @@ cosmica_status sweep(cosmica_ctx* ctx, const cosmica_job* jobs, int n_jobs, int 
         if ((st = consider(cosmica_launch{blk, 0, best.chunk, best.order})) != COSMICA_OK) break;
     if (st == COSMICA_OK) {
         int occ = 0;
-        if (occupancy_propagate(model, precision, best.block, &occ) != hipSuccess || occ < 1) occ = 1;
+        bool shaped_jobs = false;
+        for (int j = 0; j < n_jobs; ++j) shaped_jobs |= job_shaped(copy_job(&jobs[j]));
+        if (occupancy_propagate(model, precision, best.block, shaped_jobs ? 1 : 0, &occ) !=
+                hipSuccess ||
+            occ < 1)
+            occ = 1;
         const cosmica_launch base = best;
         for (int bpc : {occ - occ / 4, occ / 2})
             if (bpc >= 1 && bpc < occ &&
@@ -1191,7 +1308,7 @@ struct ServeGroup {
     std::vector<ChunkDev> carry;               // chunks to hand to the next slice
     std::vector<Req*> resident;
     std::vector<Req*> releasing;               // cancelled, freed after the next slice
-    int grid = 0, block = 256;
+    int grid = 0, grid_shaped = 0, block = 256;
     uint32_t n_chunks_last = 0;
     explicit ServeGroup(cosmica_ctx* c) : ctx(c), mem(c) {}
 };
@@ -1246,7 +1363,10 @@ cosmica_status group_create(cosmica_ctx* ctx, int model, int prec, ServeGroup** 
     if ((st = g->mem.alloc(&g->segs_d, (size_t)S * B)) != COSMICA_OK) return st;
     const cosmica_launch& L = ctx->launch[model][prec];
     g->block = L.block;
-    g->grid = grid_for(ctx, model, prec, L, ~0ull >> 8);
+    g->grid = grid_for(ctx, model, prec, L, ~0ull >> 8, false);
+    // slices with a squashed heliosphere run the kernel that tests it; the
+    // parking arrays are sized for the larger grid
+    g->grid_shaped = std::min(g->grid, grid_for(ctx, model, prec, L, ~0ull >> 8, true));
     g->susp_cap = (uint32_t)g->grid * (uint32_t)g->block;
     if ((st = g->mem.alloc(&g->susp[0], g->susp_cap)) != COSMICA_OK) return st;
     if ((st = g->mem.alloc(&g->susp[1], g->susp_cap)) != COSMICA_OK) return st;
@@ -1432,8 +1552,11 @@ cosmica_status launch_slice(ServeGroup* g)
     a.job_done = g->done_d;
     a.leftover = g->left_d;
     a.leftover_count = g->counters_d + 3;
+    // every request holding a slot may have particles in this slice
+    for (const Req* q : g->resident) a.shaped |= job_shaped(q->job) ? 1u : 0u;
+    for (const Req* q : g->releasing) a.shaped |= job_shaped(q->job) ? 1u : 0u;
     g->n_chunks_last = nch;
-    HIP_TRY(launch_model<R>(g->model, a, g->grid, g->block, s));
+    HIP_TRY(launch_model<R>(g->model, a, a.shaped ? g->grid_shaped : g->grid, g->block, s));
     // the host copy of the chunk list must outlive the asynchronous upload
     HIP_TRY(hipStreamSynchronize(s));
     return COSMICA_OK;

@@ -220,6 +220,27 @@ def c4_jobs(seed=42, n_sets=64, species_names=SPECIES_ORDER, n_bins=30,
     return jobs
 
 
+def c2_heliosheath_job(particles_per_bin=5000, seed=42, n_bins=20) -> dict:
+    """The config-2 job in a nose-squashed heliosphere with a heliosheath
+    (geometry drawn with seed + 1)."""
+    job = c2_job(particles_per_bin, seed, n_bins)
+    job["helio"] = draw_heliosheath(np.random.default_rng(seed + 1), job["helio"])
+    return job
+
+
+def c4_heliosheath_jobs(seed=42, **kw) -> list[dict]:
+    """The batched workload with a heliosheath geometry drawn per parameter
+    set (seed + 1 stream, so the shells, species and counts are unchanged)."""
+    jobs = c4_jobs(seed=seed, **kw)
+    rng = np.random.default_rng(seed + 1)
+    n_species = len(kw.get("species_names", SPECIES_ORDER))
+    for i in range(0, len(jobs), n_species):
+        h = draw_heliosheath(rng, jobs[i]["helio"])
+        for j in jobs[i:i + n_species]:
+            j["helio"] = copy.deepcopy(h)
+    return jobs
+
+
 def c5_requests(seed=42, rate_hz=5.0, duration_s=600.0, n_min=1000, n_max=100000,
                 bins_min=10, bins_max=50, count_scale=1.0, max_requests=None) -> list[dict]:
     """Poisson stream of spectrum requests.  Each carries one random parameter set

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_function():
 
 def test_abi_version_and_strerror():
     lib = C.load()
-    assert lib.cosmica_abi_version() == 1
+    assert lib.cosmica_abi_version() == 2
     for st in (C.OK, C.EINVAL, C.ENOMEM, C.EDEVICE, C.EBUSY, C.ECANCELED, C.ESTEPCAP,
                C.ENOTFOUND, 123):
         assert isinstance(lib.cosmica_strerror(st), bytes)
@@ -130,6 +130,43 @@ def test_hcs_requires_drift_and_wind_zero_allowed_without_drift():
     job["helio"]["v_slow_km_s"] = [0.0] * 15
     job["helio"]["v_fast_km_s"] = 0.0
     assert C.validate_job(job) == C.OK
+
+
+def _hs_job():
+    job = W.c2_job(particles_per_bin=10, n_bins=4)
+    job["helio"] = W.with_heliosheath(job["helio"], ts_nose=85.0, ts_tail=110.0, hp_nose=120.0,
+                                      hp_tail=160.0, kappa0_hs=0.5e22, v_hs=150.0,
+                                      tilt_hs_deg=30.0)
+    return job
+
+
+@pytest.mark.parametrize("field,value", [
+    ("r_boundary_nose_au", 170.0),   # nose beyond the tail
+    ("r_boundary_nose_au", 0.5),     # injection point outside toward the nose
+    ("r_boundary_nose_au", -3.0),
+    ("nose_theta_rad", float("nan")),
+    ("heliosheath", 2),
+    ("ts_nose_au", 0.5),             # shock inside the injection point
+    ("ts_nose_au", 120.0),           # nose beyond the tail
+    ("ts_tail_au", float("inf")),
+    ("kappa0_hs_cm2_s", 0.0),
+    ("v_hs_km_s", 0.0),              # drift needs a wind
+    ("tilt_hs_deg", 90.0),
+])
+def test_invalid_heliosheath_fields_are_rejected(field, value):
+    job = _hs_job()
+    assert C.validate_job(job) == C.OK
+    job["helio"][field] = value
+    assert C.validate_job(job) == C.EINVAL
+
+
+def test_squashed_heliosphere_is_3d_only():
+    job = W.c1_job()
+    job["helio"]["r_boundary_nose_au"] = 80.0
+    assert C.validate_job(job) == C.EINVAL
+    job = W.c1_job()
+    job["helio"]["heliosheath"] = 1
+    assert C.validate_job(job) == C.EINVAL
 
 
 def test_bins_and_counts_are_checked():
