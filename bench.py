@@ -190,6 +190,22 @@ def cpu_baseline(seconds_target=15.0):
                       f"{steps} steps in {wall:.1f} s"}
 
 
+def heliosheath_leg(eng, sync) -> dict:
+    """One pass of the batched workload in a nose-squashed heliosphere with a
+    termination shock and heliosheath (drawn per parameter set), mixed."""
+    hjobs = W.c4_heliosheath_jobs()
+    hplan = eng.plan(hjobs, "mixed")
+    hw, hprop, _, hn, _ = time_plan(eng, hplan, 1, 0, sync)
+    hplan.destroy()
+    ops = sum(OPS_PER_STEP["3d"].values())
+    return {"workload": "the batched workload in a nose-squashed heliosphere with a "
+                        "termination shock and heliosheath drawn per parameter set",
+            "steps_per_s": float(hn[0] / hw), "ms_per_pass": round(hw * 1e3, 3),
+            "spectra_per_hour": round(len(hjobs) / hw * 3600.0, 1), "steps": int(hn[0]),
+            "particles": W.total_particles(hjobs),
+            "frac": round(ops * hn[0] / (hprop[0] * 1e-3) / 1e12 / PEAK_TOPS["mixed"], 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,17 +216,20 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-heliosheath", action="store_true")
+    ap.add_argument("--heliosheath-only", action="store_true",
+                    help="time only the heliosheath workload (for profiling)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
                     help="time the batched pass only (profiling runs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
-    if args.batched_only:
-        args.no_plain = args.no_serve = args.no_cpu = True
+    if args.batched_only or args.heliosheath_only:
+        args.no_plain = args.no_serve = args.no_cpu = args.no_heliosheath = True
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the quasi-particles are "
-              "independent and a multi-GPU run would shard whole bins; see the design notes.",
+              "independent, and a run over several GPUs would give each one whole bins (bin_offset).",
               file=sys.stderr)
         sys.exit(2)
 
@@ -231,6 +250,10 @@ def main():
     launch = tuned_engine_launch(eng, {"mixed": jobs} if pjobs is None else
                                  {"mixed": jobs, "fp64": pjobs})
     log("launch shapes:", launch)
+    if args.heliosheath_only:
+        print(json.dumps(heliosheath_leg(eng, sync)), flush=True)
+        eng.close()
+        return
 
     n_particles = W.total_particles(jobs)
     plan = eng.plan(jobs, "mixed")
@@ -268,6 +291,11 @@ def main():
                  "fp64_ops_frac": round(ops * p_rate / 1e12 / PEAK_TOPS["fp64"], 4)}
         log("plain fp64:", plain)
 
+    helio = None
+    if not args.no_heliosheath:
+        helio = heliosheath_leg(eng, sync)
+        log("heliosheath:", helio)
+
     serving = None
     if not args.no_serve:
         serving = serve(eng, args.serve_seconds, 5.0, "mixed")
@@ -291,7 +319,7 @@ def main():
                    "particles": n_particles, "spectra": len(jobs), "seed": 42,
                    "launch": launch["mixed"], "parallelism": "1 GPU"},
         "spectra_per_hour": round(spectra_per_hour, 1),
-        "plain_fp64": plain, "serving": serving,
+        "plain_fp64": plain, "heliosheath": helio, "serving": serving,
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

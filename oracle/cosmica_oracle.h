@@ -17,9 +17,11 @@
  *   - the exit-rigidity histogram and the LIS-weighted modulated flux of
  *     Eq.(4) (Sec. III, Sec. IV.A);
  *   - random numbers from the Philox4x32-10 counter-based generator cited in
- *     Sec. IV.A (Salmon et al., SC'11), written from that paper.
+ *     Sec. IV.A (Salmon et al., SC'11), written from that paper;
+ *   - optionally the heliosphere squashed toward its nose with a heliosheath
+ *     beyond the termination shock (Sec. II.B), with its shape as a reading.
  * Every coefficient the paper leaves to its external references is a stated
- * reading (the design notes list them); the formulas are the ones spelled out
+ * reading marked as such; the formulas are the ones spelled out
  * next to each function below.
  *
  * Units inside the oracle: AU, s, GV, GeV.  Inputs arrive in the physical units
