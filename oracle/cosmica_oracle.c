@@ -472,6 +472,13 @@ int orc_propagate(const orc_params* p, uint32_t bin_index, double P0_gv, uint32_
 {
     derived d;
     if (derive(p, &d) != 0 || !(P0_gv > 0.0)) return -1;
+    /* every orbit position lies inside the heliopause */
+    for (uint32_t k = 0; k < p->n_orbit; ++k) {
+        const double* q = p->orbit + 3 * (size_t)k;
+        int32_t reg;
+        if (!(q[0] > 0.0) || !(q[1] > 0.0) || !(q[1] < ORC_PI)) return -1;
+        if (orc_locate(p, q[0], q[1], q[2], &reg) != 0) return -1;
+    }
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #pragma omp parallel for schedule(dynamic, 16)
@@ -479,6 +486,12 @@ int orc_propagate(const orc_params* p, uint32_t bin_index, double P0_gv, uint32_
     for (int64_t i = 0; i < (int64_t)count; ++i) {
         uint32_t particle = first + (uint32_t)i;
         pstate s = {p->r0_au, p->theta0_rad, p->phi0_rad, P0_gv, 0.0, 0u};
+        if (p->n_orbit > 0) {
+            const double* q = p->orbit + 3 * (size_t)(particle % p->n_orbit);
+            s.r = q[0];
+            s.th = q[1];
+            s.ph = q[2];
+        }
         int rc = run(p, &d, bin_index, particle, &s, UINT64_MAX);
         orc_exit* e = &out[i];
         e->P = s.P;

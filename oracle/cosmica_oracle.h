@@ -80,6 +80,14 @@ typedef struct {
     /* heliosheath region: diffusion coefficient, one wind speed (no fast/slow
      * band), current-sheet tilt */
     double kappa0_hs_cm2_s, v_hs_km_s, tilt_hs_deg;
+    /* Moving detection point (Sec. IV.A: the sample of a bin is divided among
+     * the positions of a spacecraft orbit).  READING: n_orbit positions sampled
+     * at equal time steps along the orbit, orbit[3k..3k+2] = (r [AU], theta,
+     * phi); particle i starts at position i mod n_orbit.  n_orbit = 0: every
+     * particle starts at (r0_au, theta0_rad, phi0_rad). */
+    const double* orbit;
+    uint32_t n_orbit;
+    uint32_t pad2;
 } orc_params;
 
 enum { ORC_FLAG_CAPPED = 1, ORC_FLAG_NAN = 2 };

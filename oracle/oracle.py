@@ -71,6 +71,9 @@ class OrcParams(ctypes.Structure):
         ("kappa0_hs_cm2_s", ctypes.c_double),
         ("v_hs_km_s", ctypes.c_double),
         ("tilt_hs_deg", ctypes.c_double),
+        ("orbit", ctypes.POINTER(ctypes.c_double)),
+        ("n_orbit", ctypes.c_uint32),
+        ("pad2", ctypes.c_uint32),
     ]
 
 
@@ -187,6 +190,12 @@ def params(job: dict, **override) -> OrcParams:
     p.kappa0_hs_cm2_s = h.get("kappa0_hs_cm2_s", 0.0)
     p.v_hs_km_s = h.get("v_hs_km_s", 0.0)
     p.tilt_hs_deg = h.get("tilt_hs_deg", 0.0)
+    orbit = job.get("orbit")
+    if orbit is not None and len(orbit) > 0:
+        arr = np.ascontiguousarray(orbit, dtype=np.float64).reshape(-1, 3)
+        p._orbit_keep = arr  # the struct points into this array
+        p.orbit = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.n_orbit = len(arr)
     return p
 
 

@@ -241,6 +241,52 @@ def c4_heliosheath_jobs(seed=42, **kw) -> list[dict]:
     return jobs
 
 
+def kepler_orbit(n, a_au, ecc, incl_deg, arg_peri_deg=0.0, node_deg=0.0) -> np.ndarray:
+    """n positions (r [AU], theta, phi) at equal time steps along a heliocentric
+    Kepler orbit (semi-major axis a, eccentricity, inclination to the solar
+    equator, argument of perihelion, longitude of the ascending node)."""
+    M = 2.0 * math.pi * (np.arange(n) + 0.5) / n  # mean anomaly, equal times
+    E = M.copy()
+    for _ in range(50):  # Newton on E - e sin E = M
+        E = E - (E - ecc * np.sin(E) - M) / (1.0 - ecc * np.cos(E))
+    nu = 2.0 * np.arctan2(math.sqrt(1 + ecc) * np.sin(E / 2), math.sqrt(1 - ecc) * np.cos(E / 2))
+    r = a_au * (1.0 - ecc * np.cos(E))
+    u = nu + math.radians(arg_peri_deg)  # argument of latitude
+    i, Om = math.radians(incl_deg), math.radians(node_deg)
+    x = r * (np.cos(Om) * np.cos(u) - np.sin(Om) * np.sin(u) * np.cos(i))
+    y = r * (np.sin(Om) * np.cos(u) + np.cos(Om) * np.sin(u) * np.cos(i))
+    z = r * np.sin(u) * np.sin(i)
+    th = np.arccos(np.clip(z / r, -1.0, 1.0))
+    ph = np.mod(np.arctan2(y, x), 2.0 * math.pi)
+    return np.stack([r, th, ph], 1)
+
+
+def earth_orbit(n=12) -> np.ndarray:
+    """One year of the Earth's orbit: a = 1 AU, e = 0.0167, 7.25 deg to the
+    solar equator."""
+    return kepler_orbit(n, 1.0, 0.0167, 7.25)
+
+
+def ulysses_like_orbit(n=24) -> np.ndarray:
+    """A polar out-of-ecliptic orbit like Ulysses' (a = 3.37 AU, e = 0.603,
+    79 deg to the solar equator; perihelion 1.34 AU, aphelion 5.4 AU)."""
+    return kepler_orbit(n, 3.37, 0.603, 79.1, arg_peri_deg=-90.0)
+
+
+def with_orbit(job: dict, orbit) -> dict:
+    """A copy of a job whose particles are split over the orbit positions
+    (particle i of every bin starts at position i mod len(orbit))."""
+    j = copy.deepcopy(job)
+    j["orbit"] = np.ascontiguousarray(orbit, dtype=np.float64).reshape(-1, 3).tolist()
+    return j
+
+
+def c4_orbit_jobs(seed=42, n_orbit=24, **kw) -> list[dict]:
+    """The batched workload seen from a Ulysses-like polar orbit."""
+    orbit = ulysses_like_orbit(n_orbit)
+    return [with_orbit(j, orbit) for j in c4_jobs(seed=seed, **kw)]
+
+
 def c5_requests(seed=42, rate_hz=5.0, duration_s=600.0, n_min=1000, n_max=100000,
                 bins_min=10, bins_max=50, count_scale=1.0, max_requests=None) -> list[dict]:
     """Poisson stream of spectrum requests.  Each carries one random parameter set
