@@ -206,6 +206,21 @@ def heliosheath_leg(eng, sync) -> dict:
             "frac": round(ops * hn[0] / (hprop[0] * 1e-3) / 1e12 / PEAK_TOPS["mixed"], 4)}
 
 
+def orbit_leg(eng, sync) -> dict:
+    """One pass of the batched workload seen from a moving detection point: a
+    Ulysses-like polar orbit sampled at 24 equal times, mixed."""
+    ojobs = W.c4_orbit_jobs()
+    oplan = eng.plan(ojobs, "mixed")
+    ow, oprop, _, on, _ = time_plan(eng, oplan, 1, 0, sync)
+    oplan.destroy()
+    ops = sum(OPS_PER_STEP["3d"].values())
+    return {"workload": "the batched workload with every bin split over 24 positions of a "
+                        "Ulysses-like polar orbit (1.3-5.4 AU, 79 deg inclination)",
+            "steps_per_s": float(on[0] / ow), "ms_per_pass": round(ow * 1e3, 3),
+            "spectra_per_hour": round(len(ojobs) / ow * 3600.0, 1), "steps": int(on[0]),
+            "frac": round(ops * on[0] / (oprop[0] * 1e-3) / 1e12 / PEAK_TOPS["mixed"], 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +232,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-heliosheath", action="store_true")
+    ap.add_argument("--no-orbit", action="store_true")
     ap.add_argument("--heliosheath-only", action="store_true",
                     help="time only the heliosheath workload (for profiling)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -226,7 +242,7 @@ def main():
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.batched_only or args.heliosheath_only:
-        args.no_plain = args.no_serve = args.no_cpu = args.no_heliosheath = True
+        args.no_plain = args.no_serve = args.no_cpu = args.no_heliosheath = args.no_orbit = True
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the quasi-particles are "
               "independent, and a run over several GPUs would give each one whole bins (bin_offset).",
@@ -296,6 +312,11 @@ def main():
         helio = heliosheath_leg(eng, sync)
         log("heliosheath:", helio)
 
+    orbit = None
+    if not args.no_orbit:
+        orbit = orbit_leg(eng, sync)
+        log("orbit:", orbit)
+
     serving = None
     if not args.no_serve:
         serving = serve(eng, args.serve_seconds, 5.0, "mixed")
@@ -319,7 +340,7 @@ def main():
                    "particles": n_particles, "spectra": len(jobs), "seed": 42,
                    "launch": launch["mixed"], "parallelism": "1 GPU"},
         "spectra_per_hour": round(spectra_per_hour, 1),
-        "plain_fp64": plain, "heliosheath": helio, "serving": serving,
+        "plain_fp64": plain, "heliosheath": helio, "orbit": orbit, "serving": serving,
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

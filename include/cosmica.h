@@ -31,11 +31,12 @@
 extern "C" {
 #endif
 
-#define COSMICA_ABI_VERSION 2
+#define COSMICA_ABI_VERSION 3
 #define COSMICA_MAX_REGIONS 15 /* radial shells of the inner heliosphere (Sec. II.B) */
 #define COSMICA_REGION_HELIOSHEATH 15 /* region index of the heliosheath */
 #define COSMICA_NHIST 129      /* 128 bins of log10(P_ex/P0) over [0,3) + overflow */
 #define COSMICA_MAX_STEP_CAP 16777215u
+#define COSMICA_MAX_ORBIT 1024 /* positions of a moving detection point */
 
 typedef enum {
     COSMICA_OK = 0,
@@ -130,6 +131,18 @@ typedef struct {
     uint32_t bin_offset;                /* bin b draws the streams of bin bin_offset + b, so
                                            the bins of one spectrum can be split over jobs
                                            (or devices) with identical results */
+    /* Moving detection point (Sec. IV.A: the sample is divided among the
+     * positions of a spacecraft orbit, so the flux integrates over the
+     * mission): n_orbit positions at equal time steps, orbit[3k..3k+2] =
+     * (r [AU], theta, phi); particle i of every bin starts at position
+     * i mod n_orbit, and each bin's flux is the mean over all its particles.
+     * Positions lie inside the heliopause, theta in (0, pi); n_orbit <=
+     * COSMICA_MAX_ORBIT.  n_orbit = 0 (orbit may be NULL): every particle
+     * starts at the heliosphere's (r0_au, theta0_rad, phi0_rad).  The library
+     * copies the positions. */
+    const double* orbit;
+    uint32_t n_orbit;
+    uint32_t reserved;
 } cosmica_job;
 
 /* Per-particle exit record (optional output, for checks). */

@@ -71,7 +71,8 @@ class Job(ctypes.Structure):
                 ("rigidity_gv", c_double_p), ("particles_per_bin", c_u32_p),
                 ("n_bins", ctypes.c_int32), ("job_tag", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("step_cap", ctypes.c_uint32),
-                ("bin_offset", ctypes.c_uint32)]
+                ("bin_offset", ctypes.c_uint32), ("orbit", c_double_p),
+                ("n_orbit", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class Exit(ctypes.Structure):
@@ -209,11 +210,16 @@ class _JobPack:
                                float(sp["lis_index"]))
         self.rig = np.ascontiguousarray(job["rigidity_gv"], dtype=np.float64)
         self.cnt = np.ascontiguousarray(job["particles_per_bin"], dtype=np.uint32)
+        orbit = job.get("orbit")
+        self.orbit = (np.ascontiguousarray(orbit, dtype=np.float64).reshape(-1, 3)
+                      if orbit is not None and len(orbit) else np.zeros((0, 3)))
         self.job = Job(ctypes.pointer(self.helio), ctypes.pointer(self.species),
                        self.rig.ctypes.data_as(c_double_p), self.cnt.ctypes.data_as(c_u32_p),
                        len(self.rig), int(job["job_tag"]) & 0xffffffff,
                        int(job["seed"]) & (2**64 - 1), int(job.get("step_cap", 0)),
-                       int(job.get("bin_offset", 0)))
+                       int(job.get("bin_offset", 0)),
+                       self.orbit.ctypes.data_as(c_double_p) if len(self.orbit) else None,
+                       len(self.orbit), 0)
         self.n_bins = len(self.rig)
         self.total = int(self.cnt.sum())
 

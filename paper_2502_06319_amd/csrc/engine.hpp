@@ -35,6 +35,7 @@ struct alignas(16) JobDev {
     double hp_d2, hp_prod;       // heliopause: Rt - Rn, Rn Rt
     double ts_nose, ts_tail;     // termination shock (ts_nose = +inf: no heliosheath)
     double ts_d2, ts_prod;
+    uint32_t orbit_off, n_orbit;  // moving detection point: first entry and count (0: r0, th0, ph0)
     R sin_tn, cos_tn, ph_n, pad_n;  // nose direction: sin, cos of its colatitude; longitude
     R vf;          // fast wind [AU/s]
     R omega;       // solar rotation [rad/s]
@@ -55,6 +56,11 @@ struct alignas(16) JobDev {
 template <typename R>
 struct alignas(16) RegionDev {
     R k0, vs, alpha, tana, om_vs, vf, pad1, pad2;
+};
+
+// One position of a moving detection point.
+struct alignas(16) OrbitDev {
+    double r, th, ph, pad;
 };
 
 // One (job, rigidity bin) segment of the flat work index.
@@ -83,6 +89,7 @@ template <typename R>
 struct PropArgs {
     const JobDev<R>* jobs;
     const RegionDev<R>* regions;  // jobs * kRegionStride
+    const OrbitDev* orbit;        // orbit positions, indexed by JobDev::orbit_off
     const SegmentDev* segs;
     const ChunkDev* chunks;
     uint32_t n_chunks;

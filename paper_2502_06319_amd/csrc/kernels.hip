@@ -590,9 +590,17 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
                 J = load_job(Jd);
                 jd = a.jobs + job;
                 reg = a.regions + (size_t)job * kRegionStride;
-                s.r = Jd.r0;
-                s.th = (R)Jd.th0;
-                s.ph = (R)Jd.ph0;
+                if (Jd.n_orbit == 0) {
+                    s.r = Jd.r0;
+                    s.th = (R)Jd.th0;
+                    s.ph = (R)Jd.ph0;
+                } else {
+                    // moving detection point: particle i starts at position i mod n
+                    const OrbitDev o = a.orbit[Jd.orbit_off + pid % Jd.n_orbit];
+                    s.r = o.r;
+                    s.th = (R)o.th;
+                    s.ph = (R)o.ph;
+                }
                 s.P = sg.P0;
                 s.t = 0.0;
                 s.n = 0u;

@@ -68,9 +68,22 @@ struct JobCopy {
     uint32_t cap = kDefaultStepCap;
     uint32_t bin_offset = 0;
     uint64_t total = 0;
+    std::vector<double> orbit;  // 3 per position
 };
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// A point strictly inside the heliopause (the squashed surface of cosmica.h
+// for a 3D heliosphere with a nose distance, else the sphere r_boundary_au).
+bool inside_heliopause(const cosmica_helio& h, double r, double th, double ph)
+{
+    const double rt = h.r_boundary_au;
+    const double rn = h.r_boundary_nose_au > 0.0 ? h.r_boundary_nose_au : rt;
+    if (h.model != COSMICA_MODEL_3D || rn == rt) return r < rt;
+    const double cpsi = std::sin(th) * std::sin(h.nose_theta_rad) * std::cos(ph - h.nose_phi_rad) +
+                        std::cos(th) * std::cos(h.nose_theta_rad);
+    return r * r + (rt - rn) * r * cpsi < rn * rt;
+}
 
 cosmica_status validate(const cosmica_job* j)
 {
@@ -137,6 +150,15 @@ cosmica_status validate(const cosmica_job* j)
     }
     if (total >= (1ull << 32)) return COSMICA_EINVAL;
     if ((uint64_t)j->bin_offset + (uint64_t)j->n_bins > (1ull << 32)) return COSMICA_EINVAL;
+    // moving detection point: positions inside the heliopause
+    if (j->n_orbit > COSMICA_MAX_ORBIT || (j->n_orbit > 0 && j->orbit == nullptr))
+        return COSMICA_EINVAL;
+    for (uint32_t k = 0; k < j->n_orbit; ++k) {
+        const double* q = j->orbit + 3 * (size_t)k;
+        if (!finite_pos(q[0]) || !std::isfinite(q[1]) || !std::isfinite(q[2])) return COSMICA_EINVAL;
+        if (h.model == COSMICA_MODEL_3D && (!(q[1] > 0.0) || !(q[1] < kPiH))) return COSMICA_EINVAL;
+        if (!inside_heliopause(h, q[0], q[1], q[2])) return COSMICA_EINVAL;
+    }
     return COSMICA_OK;
 }
 
@@ -161,6 +183,7 @@ JobCopy copy_job(const cosmica_job* j)
     c.cap = j->step_cap == 0 ? kDefaultStepCap : j->step_cap;
     c.bin_offset = j->bin_offset;
     for (uint32_t n : c.cnt) c.total += n;
+    if (j->n_orbit > 0) c.orbit.assign(j->orbit, j->orbit + 3 * (size_t)j->n_orbit);
     return c;
 }
 
@@ -191,6 +214,8 @@ void make_tables(const JobCopy& jc, JobDev<R>* J, RegionDev<R>* reg, LisDev* lis
     J->ts_d2 = hs ? h.ts_tail_au - h.ts_nose_au : 0.0;
     J->ts_prod = hs ? h.ts_nose_au * h.ts_tail_au : 0.0;
     J->shaped = (hs || rb_nose != h.r_boundary_au) ? 1 : 0;
+    J->n_orbit = (uint32_t)(jc.orbit.size() / 3);
+    J->orbit_off = 0;  // set where the positions are placed
     J->sin_tn = (R)std::sin(h.nose_theta_rad);
     J->cos_tn = (R)std::cos(h.nose_theta_rad);
     const double phn = std::fmod(h.nose_phi_rad, 2.0 * kPiH);
@@ -415,6 +440,7 @@ struct cosmica_plan {
     void* jobs_d = nullptr;
     void* regions_d = nullptr;
     LisDev* lis_d = nullptr;
+    OrbitDev* orbit_d = nullptr;
     SegmentDev* segs_d = nullptr;
     ChunkDev* chunks_d[2] = {nullptr, nullptr};
     uint32_t* counters_d = nullptr;  // [head0, head1, resume_head, suspend_count, leftover_count]
@@ -449,11 +475,21 @@ cosmica_status upload_tables(cosmica_plan* p)
     std::vector<JobDev<R>> jh(nj);
     std::vector<RegionDev<R>> rh(nj * kRegionStride);
     std::vector<LisDev> lh(nj);
-    for (size_t j = 0; j < nj; ++j)
+    std::vector<OrbitDev> oh;
+    for (size_t j = 0; j < nj; ++j) {
         make_tables<R>(p->jobs[j], &jh[j], &rh[j * kRegionStride], &lh[j]);
+        jh[j].orbit_off = (uint32_t)oh.size();
+        const std::vector<double>& o = p->jobs[j].orbit;
+        for (size_t k = 0; k + 2 < o.size(); k += 3) oh.push_back(OrbitDev{o[k], o[k + 1], o[k + 2], 0.0});
+    }
     JobDev<R>* jd = nullptr;
     RegionDev<R>* rd = nullptr;
     cosmica_status st;
+    if (!oh.empty()) {
+        if ((st = p->mem.alloc(&p->orbit_d, oh.size())) != COSMICA_OK) return st;
+        HIP_TRY(hipMemcpyAsync(p->orbit_d, oh.data(), oh.size() * sizeof(OrbitDev),
+                               hipMemcpyHostToDevice, p->ctx->stream));
+    }
     if ((st = p->mem.alloc(&jd, nj)) != COSMICA_OK) return st;
     if ((st = p->mem.alloc(&rd, rh.size())) != COSMICA_OK) return st;
     if ((st = p->mem.alloc(&p->lis_d, nj)) != COSMICA_OK) return st;
@@ -463,6 +499,8 @@ cosmica_status upload_tables(cosmica_plan* p)
                            hipMemcpyHostToDevice, p->ctx->stream));
     HIP_TRY(hipMemcpyAsync(p->lis_d, lh.data(), nj * sizeof(LisDev), hipMemcpyHostToDevice,
                            p->ctx->stream));
+    // the host tables are pageable and local: the copies must be complete
+    HIP_TRY(hipStreamSynchronize(p->ctx->stream));
     p->jobs_d = jd;
     p->regions_d = rd;
     return COSMICA_OK;
@@ -480,6 +518,7 @@ cosmica_status execute_prop(cosmica_plan* p)
         std::memset(&a, 0, sizeof(a));
         a.jobs = (const JobDev<R>*)p->jobs_d;
         a.regions = (const RegionDev<R>*)p->regions_d;
+        a.orbit = p->orbit_d;
         a.segs = p->segs_d;
         a.chunks = p->chunks_d[model];
         a.n_chunks = nch;
@@ -1278,6 +1317,7 @@ struct ServeGroup {
     void* jobs_d = nullptr;
     void* regions_d = nullptr;
     LisDev* lis_d = nullptr;
+    OrbitDev* orbit_d = nullptr;  // kSlots * COSMICA_MAX_ORBIT positions
     uint32_t* cancel_d = nullptr;
     uint32_t* done_d = nullptr;
     SegmentDev* segs_d = nullptr;
@@ -1358,6 +1398,7 @@ cosmica_status group_create(cosmica_ctx* ctx, int model, int prec, ServeGroup** 
     if (st != COSMICA_OK) return st;
     const uint32_t S = ServeGroup::kSlots, B = ServeGroup::kBinsPerSlot;
     if ((st = g->mem.alloc(&g->lis_d, S)) != COSMICA_OK) return st;
+    if ((st = g->mem.alloc(&g->orbit_d, (size_t)S * COSMICA_MAX_ORBIT)) != COSMICA_OK) return st;
     if ((st = g->mem.alloc(&g->cancel_d, S)) != COSMICA_OK) return st;
     if ((st = g->mem.alloc(&g->done_d, S)) != COSMICA_OK) return st;
     if ((st = g->mem.alloc(&g->segs_d, (size_t)S * B)) != COSMICA_OK) return st;
@@ -1434,6 +1475,13 @@ cosmica_status upload_slot(ServeGroup* g, Req* q)
     make_tables<R>(q->job, &J, reg, &lis);
     hipStream_t s = g->ctx->serve_stream;
     const int slot = q->slot;
+    J.orbit_off = (uint32_t)slot * COSMICA_MAX_ORBIT;
+    std::vector<OrbitDev> oh;
+    const std::vector<double>& o = q->job.orbit;
+    for (size_t k = 0; k + 2 < o.size(); k += 3) oh.push_back(OrbitDev{o[k], o[k + 1], o[k + 2], 0.0});
+    if (!oh.empty())
+        HIP_TRY(hipMemcpyAsync(g->orbit_d + J.orbit_off, oh.data(), oh.size() * sizeof(OrbitDev),
+                               hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync((JobDev<R>*)g->jobs_d + slot, &J, sizeof(J), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync((RegionDev<R>*)g->regions_d + (size_t)slot * kRegionStride, reg,
                            sizeof(reg), hipMemcpyHostToDevice, s));
@@ -1535,6 +1583,7 @@ cosmica_status launch_slice(ServeGroup* g)
     std::memset(&a, 0, sizeof(a));
     a.jobs = (const JobDev<R>*)g->jobs_d;
     a.regions = (const RegionDev<R>*)g->regions_d;
+    a.orbit = g->orbit_d;
     a.segs = g->segs_d;
     a.chunks = g->chunks_d;
     a.n_chunks = nch;

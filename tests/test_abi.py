@@ -39,7 +39,7 @@ def test_library_exports_every_declared_function():
 
 def test_abi_version_and_strerror():
     lib = C.load()
-    assert lib.cosmica_abi_version() == 2
+    assert lib.cosmica_abi_version() == 3
     for st in (C.OK, C.EINVAL, C.ENOMEM, C.EDEVICE, C.EBUSY, C.ECANCELED, C.ESTEPCAP,
                C.ENOTFOUND, 123):
         assert isinstance(lib.cosmica_strerror(st), bytes)
@@ -167,6 +167,24 @@ def test_squashed_heliosphere_is_3d_only():
     job = W.c1_job()
     job["helio"]["heliosheath"] = 1
     assert C.validate_job(job) == C.EINVAL
+
+
+def test_orbit_positions_are_checked():
+    job = W.with_orbit(W.c2_job(particles_per_bin=10, n_bins=4), W.ulysses_like_orbit(24))
+    assert C.validate_job(job) == C.OK
+    for bad in ([[121.0, 1.0, 0.0]],          # beyond the 120 AU heliopause
+                [[5.0, 0.0, 0.0]],            # on the pole
+                [[-1.0, 1.0, 0.0]],
+                [[5.0, 1.0, float("nan")]]):
+        assert C.validate_job(W.with_orbit(job, bad)) == C.EINVAL, bad
+    assert C.validate_job(W.with_orbit(job, [[2.0, 1.0, 0.0]] * 1025)) == C.EINVAL
+    # squashed heliopause: 130 AU is inside toward the tail, outside toward the nose
+    hs = _hs_job()
+    h = hs["helio"]
+    nose = [130.0, h["nose_theta_rad"], h["nose_phi_rad"]]
+    tail = [130.0, math.pi - h["nose_theta_rad"], h["nose_phi_rad"] + math.pi]
+    assert C.validate_job(W.with_orbit(hs, [tail])) == C.OK
+    assert C.validate_job(W.with_orbit(hs, [nose])) == C.EINVAL
 
 
 def test_bins_and_counts_are_checked():
