@@ -137,6 +137,7 @@ static int derive(const orc_params* p, derived* d)
     if (!(d->Rb_nose <= d->Rb) || !(d->Rb_nose > p->r0_au)) return -1;
     d->hs = p->heliosheath != 0;
     if (p->model == 0 && (d->hs || d->Rb_nose != d->Rb)) return -1; /* 3D only */
+    if (p->formulation != 0 && (p->formulation != 1 || p->model == 0)) return -1;
     d->ts_nose = p->ts_nose_au;
     d->ts_tail = p->ts_tail_au;
     if (d->hs && !(d->ts_nose > p->r0_au && d->ts_nose <= d->ts_tail)) return -1;
@@ -378,6 +379,7 @@ void orc_coeffs_3d(const orc_params* p, double P, double r, double theta, double
 typedef struct {
     double r, th, ph, P, t;
     uint32_t n;
+    double T, lam; /* energy form: kinetic energy [GeV] and the loss integral */
 } pstate;
 
 static void step1d(const orc_params* p, const derived* d, uint32_t bin, uint32_t particle,
@@ -448,6 +450,72 @@ static void step3d(const orc_params* p, const derived* d, uint32_t bin, uint32_t
     s->n = s->n + 1;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Energy form, Eq.(1).  Written for the backward Kolmogorov form of Eq.(2),  */
+/* the spatial terms are those of the momentum form (diffusion, convection,   */
+/* drift); the energy term (1/3)(div V) d(alpha T U)/dT splits into the       */
+/* advection (1/3)(div V) alpha T dU/dT and a term proportional to U, which   */
+/* with the -(div V) U of the convective divergence is the loss               */
+/*   L = (div V) [1 - (1/3) d(alpha T)/dT],  d(alpha T)/dT = 1 + (M/(T+M))^2, */
+/* alpha = (T + 2M)/(T + M), T the kinetic energy of the particle and M its   */
+/* rest energy (per nucleon both, or both per particle: alpha is a ratio).    */
+/* So dT = (1/3)(div V) alpha T ds, and each step adds L ds to the exponent   */
+/* of Eq.(4).  div V = 2V/r for the radial wind.                              */
+/* ------------------------------------------------------------------------ */
+static double rigidity_of_T(const derived* d, double T)
+{
+    return sqrt(T * (T + 2.0 * d->mass)) / d->absZ;
+}
+
+static void step3d_energy(const orc_params* p, const derived* d, uint32_t bin,
+                          uint32_t particle, pstate* s)
+{
+    uint32_t ctr[4] = {s->n, particle, bin, p->job_tag};
+    double z[4];
+    orc_normals(p->seed, ctr, z);
+    double z2 = p->flip_z2 ? -z[2] : z[2];
+    double P = rigidity_of_T(d, s->T);
+    orc_coeffs c;
+    coeffs3d(p, d, P, s->r, s->th, s->ph, &c);
+    double dt = c.dt;
+    double sdt = sqrt(dt);
+    double st = sin(s->th);
+    double M = d->mass;
+    double divV = 2.0 * c.V / s->r;
+    double alpha = (s->T + 2.0 * M) / (s->T + M);
+    double dalphaT = 1.0 + (M / (s->T + M)) * (M / (s->T + M));
+    double AT = divV / 3.0 * alpha * s->T;
+    double L = divV * (1.0 - dalphaT / 3.0);
+    double r1 = s->r + c.A[0] * dt + c.Brr * z[0] * sdt;
+    double th1 = s->th + c.A[1] * dt + c.Btt * z2 * sdt / s->r;
+    double ph1 = s->ph + c.A[2] * dt + (c.Bpr * z[0] + c.Bpp * z[1]) * sdt / (s->r * st);
+    double T1 = s->T + AT * dt;
+    if (r1 < 0.0) {
+        r1 = -r1;
+        th1 = ORC_PI - th1;
+        ph1 = ph1 + ORC_PI;
+    }
+    if (th1 < 0.0) {
+        th1 = -th1;
+        ph1 = ph1 + ORC_PI;
+    }
+    th1 = fmod(th1, 2.0 * ORC_PI);
+    if (th1 > ORC_PI) {
+        th1 = 2.0 * ORC_PI - th1;
+        ph1 = ph1 + ORC_PI;
+    }
+    ph1 = fmod(ph1, 2.0 * ORC_PI);
+    if (ph1 < 0.0) ph1 += 2.0 * ORC_PI;
+    s->r = r1;
+    s->th = th1;
+    s->ph = ph1;
+    s->T = T1;
+    s->P = rigidity_of_T(d, T1);
+    s->lam = s->lam + L * dt;
+    s->t = s->t + dt;
+    s->n = s->n + 1;
+}
+
 /* Runs steps until exit (r >= R_b), NaN, the step cap, or max_steps more steps.
  * Returns 1 exited, 0 still inside, 2 capped, 3 NaN. */
 static int run(const orc_params* p, const derived* d, uint32_t bin, uint32_t particle,
@@ -457,6 +525,8 @@ static int run(const orc_params* p, const derived* d, uint32_t bin, uint32_t par
         if (s->n >= p->step_cap) return 2;
         if (p->model == 0)
             step1d(p, d, bin, particle, s);
+        else if (p->formulation == 1)
+            step3d_energy(p, d, bin, particle, s);
         else
             step3d(p, d, bin, particle, s);
         if (isnan(s->r) || isnan(s->P)) return 3;
@@ -485,7 +555,9 @@ int orc_propagate(const orc_params* p, uint32_t bin_index, double P0_gv, uint32_
 #endif
     for (int64_t i = 0; i < (int64_t)count; ++i) {
         uint32_t particle = first + (uint32_t)i;
-        pstate s = {p->r0_au, p->theta0_rad, p->phi0_rad, P0_gv, 0.0, 0u};
+        pstate s = {p->r0_au, p->theta0_rad, p->phi0_rad, P0_gv, 0.0, 0u, 0.0, 0.0};
+        /* kinetic energy from rigidity: E^2 = (Z P)^2 + M^2 */
+        s.T = sqrt(d.absZ * P0_gv * d.absZ * P0_gv + d.mass * d.mass) - d.mass;
         if (p->n_orbit > 0) {
             const double* q = p->orbit + 3 * (size_t)(particle % p->n_orbit);
             s.r = q[0];
@@ -501,6 +573,7 @@ int orc_propagate(const orc_params* p, uint32_t bin_index, double P0_gv, uint32_
         e->phi = s.ph;
         e->n = s.n;
         e->flags = (rc == 2) ? ORC_FLAG_CAPPED : (rc == 3) ? ORC_FLAG_NAN : 0u;
+        e->loss = s.lam;
     }
     return 0;
 }
@@ -509,8 +582,8 @@ int orc_advance(const orc_params* p, uint32_t bin_index, uint32_t particle, doub
                 uint32_t* n, uint32_t max_steps)
 {
     derived d;
-    if (derive(p, &d) != 0) return -1;
-    pstate s = {state[0], state[1], state[2], state[3], state[4], *n};
+    if (derive(p, &d) != 0 || p->formulation != 0) return -1; /* momentum form only */
+    pstate s = {state[0], state[1], state[2], state[3], state[4], *n, 0.0, 0.0};
     int rc = run(p, &d, bin_index, particle, &s, max_steps);
     state[0] = s.r;
     state[1] = s.th;
@@ -532,10 +605,22 @@ double orc_lis(const orc_params* p, double P_gv)
     return p->lis_norm * pow(P_gv, -p->lis_index);
 }
 
+/* Contribution of one exit record to J_mod(P0): momentum form
+ * P0^2 J_LIS(P_ex) / P_ex^2 (f conserved); energy form, where U = 4 pi p^2 f / v
+ * is transported with the loss weight, beta0 / beta_ex J_LIS(P_ex) exp(-loss). */
+static double contribution(const orc_params* p, const derived* d, double P0, const orc_exit* e)
+{
+    if (p->formulation == 1)
+        return beta_of(d, P0) / beta_of(d, e->P) * orc_lis(p, e->P) * exp(-e->loss);
+    return P0 * P0 * (orc_lis(p, e->P) / (e->P * e->P));
+}
+
 void orc_reduce_bin(const orc_params* p, double P0_gv, const orc_exit* rec, uint32_t n,
                     orc_bin_result* res)
 {
     memset(res, 0, sizeof(*res));
+    derived d;
+    if (derive(p, &d) != 0) return;
     double sw = 0.0, st = 0.0;
     uint32_t used = 0;
     for (uint32_t i = 0; i < n; ++i) {
@@ -549,8 +634,7 @@ void orc_reduce_bin(const orc_params* p, double P0_gv, const orc_exit* rec, uint
             continue;
         }
         double P = rec[i].P;
-        double w = orc_lis(p, P) / (P * P);
-        sw += w;
+        sw += contribution(p, &d, P0_gv, &rec[i]);
         st += rec[i].t;
         used++;
         /* histogram of log10(P_ex / P0) over [0, 3) in 128 bins + overflow */
@@ -563,18 +647,17 @@ void orc_reduce_bin(const orc_params* p, double P0_gv, const orc_exit* rec, uint
     res->n_used = used;
     if (used > 0) {
         double N = (double)used;
-        res->flux = P0_gv * P0_gv * sw / N;
+        res->flux = sw / N;
         res->mean_exit_time_s = st / N;
         if (used > 1) {
-            /* standard error of the mean weight: two-pass sample variance */
+            /* standard error of the mean contribution: two-pass sample variance */
             double mean = sw / N, ss = 0.0;
             for (uint32_t i = 0; i < n; ++i) {
                 if (rec[i].flags & (ORC_FLAG_CAPPED | ORC_FLAG_NAN)) continue;
-                double P = rec[i].P;
-                double dw = orc_lis(p, P) / (P * P) - mean;
+                double dw = contribution(p, &d, P0_gv, &rec[i]) - mean;
                 ss += dw * dw;
             }
-            res->flux_se = P0_gv * P0_gv * sqrt(ss / (N - 1.0) / N);
+            res->flux_se = sqrt(ss / (N - 1.0) / N);
         }
     }
 }

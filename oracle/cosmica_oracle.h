@@ -87,7 +87,10 @@ typedef struct {
      * particle starts at (r0_au, theta0_rad, phi0_rad). */
     const double* orbit;
     uint32_t n_orbit;
-    uint32_t pad2;
+    /* 0: momentum form, Eq.(5) with L = 0 (Sec. VI, Version 6).  1: energy
+     * form, Eq.(1) (the form of Versions 0-3), whose backward SDE carries the
+     * loss term of Eq.(2) and the exponential weight of Eq.(4); 3D model only. */
+    int32_t formulation;
 } orc_params;
 
 enum { ORC_FLAG_CAPPED = 1, ORC_FLAG_NAN = 2 };
@@ -98,6 +101,7 @@ typedef struct {
     double r, theta, phi;
     uint32_t n;    /* number of Euler-Maruyama steps */
     uint32_t flags;
+    double loss;   /* energy form: sum of L ds along the path; 0 in the momentum form */
 } orc_exit;
 
 /* Local SDE coefficients of the 3D model at one point, for unit-level pins. */
@@ -151,7 +155,9 @@ int orc_propagate(const orc_params* p, uint32_t bin_index, double P0_gv,
 int orc_advance(const orc_params* p, uint32_t bin_index, uint32_t particle,
                 double state[5], uint32_t* n, uint32_t max_steps);
 
-/* Per-bin results of Eq.(4) with f = J/P^2 (Sec. VI, Version 6). */
+/* Per-bin results of Eq.(4): momentum form with f = J/P^2 (Sec. VI, Version 6);
+ * energy form with U = 4 pi p^2 f / v transported and the exponential loss
+ * weight, which gives J_mod(P0) = mean(beta0 / beta_ex J_LIS(P_ex) exp(-loss)). */
 typedef struct {
     uint32_t hist[ORC_NHIST];
     double flux;        /* J_mod(P0) */

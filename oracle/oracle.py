@@ -73,18 +73,18 @@ class OrcParams(ctypes.Structure):
         ("tilt_hs_deg", ctypes.c_double),
         ("orbit", ctypes.POINTER(ctypes.c_double)),
         ("n_orbit", ctypes.c_uint32),
-        ("pad2", ctypes.c_uint32),
+        ("formulation", ctypes.c_int32),
     ]
 
 
 class OrcExit(ctypes.Structure):
     _fields_ = [("P", ctypes.c_double), ("t", ctypes.c_double), ("r", ctypes.c_double),
                 ("theta", ctypes.c_double), ("phi", ctypes.c_double),
-                ("n", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+                ("n", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("loss", ctypes.c_double)]
 
 
 EXIT_DTYPE = np.dtype([("P", "<f8"), ("t", "<f8"), ("r", "<f8"), ("theta", "<f8"),
-                       ("phi", "<f8"), ("n", "<u4"), ("flags", "<u4")])
+                       ("phi", "<f8"), ("n", "<u4"), ("flags", "<u4"), ("loss", "<f8")])
 assert EXIT_DTYPE.itemsize == ctypes.sizeof(OrcExit)
 
 
@@ -190,6 +190,7 @@ def params(job: dict, **override) -> OrcParams:
     p.kappa0_hs_cm2_s = h.get("kappa0_hs_cm2_s", 0.0)
     p.v_hs_km_s = h.get("v_hs_km_s", 0.0)
     p.tilt_hs_deg = h.get("tilt_hs_deg", 0.0)
+    p.formulation = int(job.get("formulation", 0))
     orbit = job.get("orbit")
     if orbit is not None and len(orbit) > 0:
         arr = np.ascontiguousarray(orbit, dtype=np.float64).reshape(-1, 3)
