@@ -221,6 +221,21 @@ def orbit_leg(eng, sync) -> dict:
             "frac": round(ops * on[0] / (oprop[0] * 1e-3) / 1e12 / PEAK_TOPS["mixed"], 4)}
 
 
+def energy_form_leg(eng, sync, momentum_rate) -> dict:
+    """One pass of the batched workload in the energy form of the transport
+    equation (the form of the paper's Versions 0-3), mixed, against the
+    momentum form's rate (Version 6)."""
+    ejobs = [dict(j, formulation=1) for j in W.c4_jobs()]
+    eplan = eng.plan(ejobs, "mixed")
+    ew, eprop, _, en, _ = time_plan(eng, eplan, 1, 0, sync)
+    eplan.destroy()
+    rate = float(en[0] / ew)
+    return {"workload": "the batched workload in the energy form (kinetic energy and the "
+                        "loss weight of the transport equation's energy form)",
+            "steps_per_s": rate, "ms_per_pass": round(ew * 1e3, 3), "steps": int(en[0]),
+            "momentum_over_energy": round(momentum_rate / rate, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +248,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-heliosheath", action="store_true")
     ap.add_argument("--no-orbit", action="store_true")
+    ap.add_argument("--no-energy", action="store_true")
     ap.add_argument("--heliosheath-only", action="store_true",
                     help="time only the heliosheath workload (for profiling)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -242,7 +258,8 @@ def main():
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
     if args.batched_only or args.heliosheath_only:
-        args.no_plain = args.no_serve = args.no_cpu = args.no_heliosheath = args.no_orbit = True
+        args.no_plain = args.no_serve = args.no_cpu = True
+        args.no_heliosheath = args.no_orbit = args.no_energy = True
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the quasi-particles are "
               "independent, and a run over several GPUs would give each one whole bins (bin_offset).",
@@ -312,6 +329,11 @@ def main():
         helio = heliosheath_leg(eng, sync)
         log("heliosheath:", helio)
 
+    energy = None
+    if not args.no_energy:
+        energy = energy_form_leg(eng, sync, steps_per_launch / (prop_avg * 1e-3))
+        log("energy form:", energy)
+
     orbit = None
     if not args.no_orbit:
         orbit = orbit_leg(eng, sync)
@@ -340,7 +362,8 @@ def main():
                    "particles": n_particles, "spectra": len(jobs), "seed": 42,
                    "launch": launch["mixed"], "parallelism": "1 GPU"},
         "spectra_per_hour": round(spectra_per_hour, 1),
-        "plain_fp64": plain, "heliosheath": helio, "orbit": orbit, "serving": serving,
+        "plain_fp64": plain, "energy_form": energy, "heliosheath": helio, "orbit": orbit,
+        "serving": serving,
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

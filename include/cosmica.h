@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define COSMICA_ABI_VERSION 3
+#define COSMICA_ABI_VERSION 4
 #define COSMICA_MAX_REGIONS 15 /* radial shells of the inner heliosphere (Sec. II.B) */
 #define COSMICA_REGION_HELIOSHEATH 15 /* region index of the heliosheath */
 #define COSMICA_NHIST 129      /* 128 bins of log10(P_ex/P0) over [0,3) + overflow */
@@ -142,7 +142,13 @@ typedef struct {
      * copies the positions. */
     const double* orbit;
     uint32_t n_orbit;
-    uint32_t reserved;
+    /* 0: momentum form of the transport equation, Eq.(5) (Sec. VI, Version
+     * 6; L = 0).  1: energy form, Eq.(1) (Versions 0-3), 3D only: the state
+     * carries the kinetic energy T with dT = (1/3)(div V) alpha T ds,
+     * alpha = (T + 2M)/(T + M), and the loss L = (div V)[1 - (1/3)
+     * d(alpha T)/dT] summed into the exponential weight of Eq.(4); the bin's
+     * flux is the mean of beta0/beta_ex J_LIS(P_ex) exp(-loss). */
+    int32_t formulation;
 } cosmica_job;
 
 /* Per-particle exit record (optional output, for checks). */
@@ -152,6 +158,7 @@ typedef struct {
     double r, theta, phi;
     uint32_t n;     /* Euler-Maruyama steps */
     uint32_t flags; /* 1 = hit the step cap, 2 = non-finite state */
+    double loss;    /* energy form: the summed L ds of Eq.(4); 0 in the momentum form */
 } cosmica_exit;
 
 /* Host output buffers of one job; each array has n_bins entries (hist has

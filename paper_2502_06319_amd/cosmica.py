@@ -72,17 +72,17 @@ class Job(ctypes.Structure):
                 ("n_bins", ctypes.c_int32), ("job_tag", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("step_cap", ctypes.c_uint32),
                 ("bin_offset", ctypes.c_uint32), ("orbit", c_double_p),
-                ("n_orbit", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("n_orbit", ctypes.c_uint32), ("formulation", ctypes.c_int32)]
 
 
 class Exit(ctypes.Structure):
     _fields_ = [("P", ctypes.c_double), ("t", ctypes.c_double), ("r", ctypes.c_double),
                 ("theta", ctypes.c_double), ("phi", ctypes.c_double),
-                ("n", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+                ("n", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("loss", ctypes.c_double)]
 
 
 EXIT_DTYPE = np.dtype([("P", "<f8"), ("t", "<f8"), ("r", "<f8"), ("theta", "<f8"),
-                       ("phi", "<f8"), ("n", "<u4"), ("flags", "<u4")])
+                       ("phi", "<f8"), ("n", "<u4"), ("flags", "<u4"), ("loss", "<f8")])
 assert EXIT_DTYPE.itemsize == ctypes.sizeof(Exit)
 
 
@@ -219,7 +219,7 @@ class _JobPack:
                        int(job["seed"]) & (2**64 - 1), int(job.get("step_cap", 0)),
                        int(job.get("bin_offset", 0)),
                        self.orbit.ctypes.data_as(c_double_p) if len(self.orbit) else None,
-                       len(self.orbit), 0)
+                       len(self.orbit), int(job.get("formulation", 0)))
         self.n_bins = len(self.rig)
         self.total = int(self.cnt.sum())
 

@@ -36,6 +36,8 @@ struct alignas(16) JobDev {
     double ts_nose, ts_tail;     // termination shock (ts_nose = +inf: no heliosheath)
     double ts_d2, ts_prod;
     uint32_t orbit_off, n_orbit;  // moving detection point: first entry and count (0: r0, th0, ph0)
+    int32_t energy, pad_e;        // 1: energy form (state T and the loss integral)
+    double mass;                  // rest energy [GeV], for T <-> P
     R sin_tn, cos_tn, ph_n, pad_n;  // nose direction: sin, cos of its colatitude; longitude
     R vf;          // fast wind [AU/s]
     R omega;       // solar rotation [rad/s]
@@ -77,12 +79,15 @@ struct alignas(16) ChunkDev {
 
 struct alignas(16) LisDev {
     double norm, index;
+    double abs_z, mass;  // for beta in the energy form's weight
+    int32_t energy, pad0, pad1, pad2;
 };
 
 // Suspended particle (serving slices): full state, bit-exact on resume.
 struct alignas(16) SuspendDev {
     double r, P, t, th, ph;
     uint32_t n, seg, pid, pad0;
+    double T, lam;  // energy form
 };
 
 template <typename R>
@@ -98,6 +103,7 @@ struct PropArgs {
     double* exP;
     double* exT;
     uint32_t* exNF;
+    double* exL;   // energy form: summed loss per particle (nullptr without energy-form jobs)
     double* exR;   // optional (nullptr)
     double* exTh;
     double* exPh;
@@ -110,6 +116,7 @@ struct PropArgs {
     uint32_t step_budget;         // steps per wave per launch (0xffffffff: unlimited)
     uint32_t uniform_key;         // 1: every job of the launch has the Philox key below
     uint32_t shaped;              // 1: some job of the launch has a squashed boundary or a heliosheath
+    uint32_t energy;              // 1: some job of the launch is in the energy form
     uint32_t key_lo, key_hi;
     const uint32_t* job_cancel;   // optional per-job cancel flags
     uint32_t* job_done;           // optional per-job count of finished particles
@@ -123,6 +130,7 @@ struct ReduceArgs {
     const double* exP;
     const double* exT;
     const uint32_t* exNF;
+    const double* exL;  // energy form: summed loss (may be null without energy-form jobs)
     uint32_t seg_base;  // first segment of this launch
     uint32_t* hist;     // per segment: kNHist (may be null)
     double* flux;
@@ -139,7 +147,8 @@ hipError_t launch_propagate_3d_mixed(const PropArgs<float>& a, int grid, int blo
 hipError_t launch_propagate_3d_fp64(const PropArgs<double>& a, int grid, int block, hipStream_t s);
 hipError_t launch_propagate_1d_mixed(const PropArgs<float>& a, int grid, int block, hipStream_t s);
 hipError_t launch_propagate_1d_fp64(const PropArgs<double>& a, int grid, int block, hipStream_t s);
-hipError_t occupancy_propagate(int model, int prec, int block, int shaped, int* blocks_per_cu);
+hipError_t occupancy_propagate(int model, int prec, int block, int shaped, int energy,
+                               int* blocks_per_cu);
 hipError_t launch_reduce(const ReduceArgs& a, uint32_t n_segs, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint32_t n, hipStream_t s);
 

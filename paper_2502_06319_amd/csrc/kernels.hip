@@ -174,12 +174,14 @@ struct PState {
     double r, P, t;
     R th, ph;
     uint32_t n;
+    double T, lam;  // energy form: kinetic energy [GeV] and the summed loss
 };
 
 // Local SDE coefficients of the 3D model (see cosmica.h for the model).
 template <typename R>
 struct Coef3 {
     R Ar, At, Ap, AP;      // drift of the SDE (r, theta, phi per unit time), dP/ds
+    R V;                   // local wind speed
     R Brr, Bpr, Bpp, Btt;  // B with B B^T = 2K
     R dt;
     R invr, invst;         // 1/r, 1/sin(theta) of the step
@@ -195,6 +197,8 @@ struct JobReg {
         adv_frac;
     double rb, inv_shell;
     double rb_tail, ts_nose, ts_tail;  // used by the kernels of squashed heliospheres
+    double mass;                        // rest energy, used by the energy form
+    int32_t energy;
     uint32_t seed_lo, seed_hi, job_tag, step_cap;
     int32_t nreg, drift, hcs;
 };
@@ -219,6 +223,8 @@ __device__ __forceinline__ JobReg<R> load_job(const JobDev<R>& J)
     o.rb = J.rb;
     o.inv_shell = J.inv_shell;
     o.rb_tail = J.rb_tail;
+    o.mass = J.mass;
+    o.energy = J.energy;
     o.ts_nose = J.ts_nose;
     o.ts_tail = J.ts_tail;
     o.seed_lo = J.seed_lo;
@@ -367,6 +373,7 @@ __device__ __forceinline__ void coeffs3d(const JobReg<R>& J, const RegionDev<R>&
     c.At = invr * ((kperp * cot) * invr - vdt);
     c.Ap = (dKrp - vdp) * irs;
     c.AP = ((V * P) * invr) * (R)(2.0 / 3.0);
+    c.V = V;
     // time step: min(dt_max, f_diff r^2 / k_par, f_adv r / |A_det|)
     R dt = J.dt_max;
     const R d1 = (J.diff_frac * rr) * M::rcp(kpar);
@@ -400,8 +407,19 @@ __device__ __forceinline__ void coeffs3d(const JobReg<R>& J, const RegionDev<R>&
     }
 }
 
+// Energy form (Eq.(1), rearranged into the backward form of Eq.(2)): the
+// kinetic energy T advances with dT = (1/3)(div V) alpha T ds, alpha =
+// (T + 2M)/(T + M), and each step adds L ds to the exponent of Eq.(4),
+// L = (div V)[1 - (1/3) d(alpha T)/dT] with d(alpha T)/dT = 1 + (M/(T+M))^2;
+// div V = 2V/r.  The spatial part is the momentum form's at the rigidity
+// P = sqrt(T (T + 2M)) / |Z|.
+__device__ __forceinline__ double rigidity_of_T(double T, double M, double abs_z)
+{
+    return ::sqrt(T * (T + 2.0 * M)) / abs_z;
+}
+
 // One EM step of the 3D model.  The caller tests for the exit.
-template <typename R, bool UKEY, bool SHAPED>
+template <typename R, bool UKEY, bool SHAPED, bool ENERGY>
 __device__ __forceinline__ void step3d(const JobReg<R>& J, const JobDev<R>* __restrict__ jd,
                                        const RegionDev<R>* __restrict__ reg, PState<R>& s,
                                        uint32_t pid, uint32_t bin, uint32_t k0, uint32_t k1)
@@ -410,8 +428,19 @@ __device__ __forceinline__ void step3d(const JobReg<R>& J, const JobDev<R>* __re
     R z[3];
     normals<R, 3>(UKEY ? k0 : J.seed_lo, UKEY ? k1 : J.seed_hi, s.n, pid, bin, J.job_tag, z);
     const RegionDev<R> g = reg[region_at<R, SHAPED>(J, jd, s.r, s.th, s.ph)];
+    const bool efo = ENERGY && J.energy != 0;
+    double Pd = s.P;
+    if (efo) {
+        if constexpr (std::is_same<R, float>::value) {
+            // the coefficients see the rigidity of T; binary32 suffices there
+            const float T = (float)s.T, Mr = (float)J.mass;
+            Pd = (double)(M::sqrt(T * (T + 2.0f * Mr)) * M::rcp(J.abs_z));
+        } else {
+            Pd = rigidity_of_T(s.T, J.mass, (double)J.abs_z);
+        }
+    }
     Coef3<R> c;
-    coeffs3d<R, false>(J, g, s.r, s.P, s.th, s.ph, c);
+    coeffs3d<R, false>(J, g, s.r, Pd, s.th, s.ph, c);
     const R dt = c.dt;
     const R sdt = M::sqrt(dt);
     double r1;
@@ -450,6 +479,18 @@ __device__ __forceinline__ void step3d(const JobReg<R>& J, const JobDev<R>* __re
     if (ph1 < (R)0 || ph1 >= (R)kTwoPi) {
         ph1 = M::fmod2pi(ph1);
         if (ph1 < (R)0) ph1 = ph1 + (R)kTwoPi;
+    }
+    if (efo) {
+        // (1/3) div V, alpha T and the loss at the start of the step
+        const R T = (R)s.T, Mr = (R)J.mass;
+        const R divV3 = ((R)2.0 / (R)3.0) * c.V * c.invr;
+        const R ie = M::rcp(T + Mr);
+        const R alphaT = ((T + (R)2.0 * Mr) * ie) * T;
+        const R me = Mr * ie;
+        const R L = (R)3.0 * divV3 * ((R)1.0 - ((R)1.0 + me * me) / (R)3.0);
+        s.T = s.T + (double)(divV3 * alphaT * dt);
+        s.lam = s.lam + (double)(L * dt);
+        P1 = s.P;  // the rigidity is refreshed from T when the particle leaves
     }
     s.r = r1;
     s.th = th1;
@@ -507,11 +548,11 @@ __device__ __forceinline__ uint32_t wave_uniform(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
-template <typename R, bool M3D, bool UKEY, bool SHAPED>
+template <typename R, bool M3D, bool UKEY, bool SHAPED, bool ENERGY>
 __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
 {
     const uint32_t lane = __lane_id();
-    PState<R> s = {0.0, 0.0, 0.0, (R)0, (R)0, 0u};
+    PState<R> s = {0.0, 0.0, 0.0, (R)0, (R)0, 0u, 0.0, 0.0};
     uint32_t pid = 0, bin = 0, job = 0, out = 0, seg = 0;
     JobReg<R> J = {};
     const RegionDev<R>* reg = a.regions;
@@ -542,20 +583,28 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
             }
             const uint32_t rank = lane_rank(need);
             if (!active && base + rank < a.n_resume) {
-                const SuspendDev q = a.resume[base + rank];
-                s.r = q.r;
-                s.P = q.P;
-                s.t = q.t;
-                s.th = (R)q.th;
-                s.ph = (R)q.ph;
-                s.n = q.n;
-                seg = q.seg;
-                pid = q.pid;
+                // field by field, so kernels without the energy form leave T
+                // and the loss unread
+                const SuspendDev* q = a.resume + base + rank;
+                s.r = q->r;
+                s.P = q->P;
+                s.t = q->t;
+                s.th = (R)q->th;
+                s.ph = (R)q->ph;
+                s.n = q->n;
+                seg = q->seg;
+                pid = q->pid;
                 const SegmentDev sg = a.segs[seg];
                 job = sg.job;
                 bin = sg.bin;
                 out = sg.out_offset + pid;
                 J = load_job(a.jobs[job]);
+                if (ENERGY) {
+                    // momentum-form particles may have been parked by a kernel
+                    // that did not store T and the loss
+                    s.T = J.energy ? q->T : 0.0;
+                    s.lam = J.energy ? q->lam : 0.0;
+                }
                 jd = a.jobs + job;
                 reg = a.regions + (size_t)job * kRegionStride;
                 active = true;
@@ -604,6 +653,12 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
                 s.P = sg.P0;
                 s.t = 0.0;
                 s.n = 0u;
+                if (ENERGY) {
+                    // kinetic energy from rigidity: E^2 = (Z P)^2 + M^2
+                    const double pc = (double)J.abs_z * sg.P0;
+                    s.T = ::sqrt(pc * pc + J.mass * J.mass) - J.mass;
+                    s.lam = 0.0;
+                }
                 active = true;
             }
             const uint32_t cnt = (uint32_t)__popcll(need);
@@ -636,22 +691,27 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
             bool leave = false;
             if (active) {
                 if (M3D)
-                    step3d<R, UKEY, SHAPED>(J, jd, reg, s, pid, bin, a.key_lo, a.key_hi);
+                    step3d<R, UKEY, SHAPED, ENERGY>(J, jd, reg, s, pid, bin, a.key_lo, a.key_hi);
                 else
                     step1d<R, UKEY>(J, reg, s, pid, bin, a.key_lo, a.key_hi);
                 leave = outside_boundary<R, SHAPED>(J, jd, s.r, s.th, s.ph) || !(s.P == s.P) ||
-                        s.n >= J.step_cap;
+                        (ENERGY && !(s.T == s.T)) || s.n >= J.step_cap;
             }
             ++wave_steps;
             if (__any(leave) || (sliced && wave_steps >= a.step_budget)) break;
         }
         const bool outside = active && outside_boundary<R, SHAPED>(J, jd, s.r, s.th, s.ph);
-        if (active && (outside || !(s.P == s.P) || s.n >= J.step_cap)) {
+        const bool bad_T = ENERGY && !(s.T == s.T);
+        if (active && (outside || !(s.P == s.P) || bad_T || s.n >= J.step_cap)) {
             uint32_t flags = 0;
-            if (!(s.r == s.r) || !(s.P == s.P))
+            if (!(s.r == s.r) || !(s.P == s.P) || bad_T)
                 flags = kFlagNaN;
             else if (!outside)
                 flags = kFlagCapped;
+            if (ENERGY && J.energy) {
+                s.P = rigidity_of_T(s.T, J.mass, (double)J.abs_z);
+                a.exL[out] = s.lam;
+            }
             a.exP[out] = s.P;
             a.exT[out] = s.t;
             a.exNF[out] = s.n | (flags << kFlagShift);
@@ -668,17 +728,22 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
             // taking work
             if (active) {
                 const uint32_t slot = atomicAdd(a.suspend_count, 1u);
-                SuspendDev q;
-                q.r = s.r;
-                q.P = s.P;
-                q.t = s.t;
-                q.th = (double)s.th;
-                q.ph = (double)s.ph;
-                q.n = s.n;
-                q.seg = seg;
-                q.pid = pid;
-                q.pad0 = 0;
-                a.suspend[slot] = q;
+                // an energy-form particle is only ever parked by a launch of the
+                // energy-form kernel, so only that kernel stores T and the loss
+                SuspendDev* q = a.suspend + slot;
+                q->r = s.r;
+                q->P = s.P;
+                q->t = s.t;
+                q->th = (double)s.th;
+                q->ph = (double)s.ph;
+                q->n = s.n;
+                q->seg = seg;
+                q->pid = pid;
+                q->pad0 = 0;
+                if (ENERGY) {
+                    q->T = s.T;
+                    q->lam = s.lam;
+                }
                 active = false;
             }
             launch_open = false;
@@ -686,27 +751,35 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
     }
 }
 
-template <typename R, bool M3D, bool SHAPED>
+template <typename R, bool M3D, bool SHAPED, bool ENERGY>
 static void launch_keyed(const PropArgs<R>& a, int grid, int block, hipStream_t s)
 {
     // one Philox key for the whole launch: the key schedule runs on the scalar unit
     if (a.uniform_key)
-        hipLaunchKernelGGL((k_propagate<R, M3D, true, SHAPED>), dim3(grid), dim3(block), 0, s, a);
+        hipLaunchKernelGGL((k_propagate<R, M3D, true, SHAPED, ENERGY>), dim3(grid), dim3(block),
+                           0, s, a);
     else
-        hipLaunchKernelGGL((k_propagate<R, M3D, false, SHAPED>), dim3(grid), dim3(block), 0, s, a);
+        hipLaunchKernelGGL((k_propagate<R, M3D, false, SHAPED, ENERGY>), dim3(grid), dim3(block),
+                           0, s, a);
 }
 
 template <typename R, bool M3D>
 static hipError_t launch_prop(const PropArgs<R>& a, int grid, int block, hipStream_t s)
 {
-    // squashed heliopause / heliosheath tests only where a job of the launch has them
+    // squashed heliopause / heliosheath tests, and the energy form, only where a
+    // job of the launch needs them
     if constexpr (M3D) {
-        if (a.shaped) {
-            launch_keyed<R, M3D, true>(a, grid, block, s);
-            return hipGetLastError();
-        }
+        if (a.shaped && a.energy)
+            launch_keyed<R, M3D, true, true>(a, grid, block, s);
+        else if (a.shaped)
+            launch_keyed<R, M3D, true, false>(a, grid, block, s);
+        else if (a.energy)
+            launch_keyed<R, M3D, false, true>(a, grid, block, s);
+        else
+            launch_keyed<R, M3D, false, false>(a, grid, block, s);
+    } else {
+        launch_keyed<R, M3D, false, false>(a, grid, block, s);
     }
-    launch_keyed<R, M3D, false>(a, grid, block, s);
     return hipGetLastError();
 }
 
@@ -727,30 +800,40 @@ hipError_t launch_propagate_1d_fp64(const PropArgs<double>& a, int grid, int blo
     return launch_prop<double, false>(a, grid, block, s);
 }
 
-hipError_t occupancy_propagate(int model, int prec, int block, int shaped, int* blocks_per_cu)
+template <typename R, bool M3D, bool SHAPED, bool ENERGY>
+static void keyed_variants(const void** f)
+{
+    f[0] = (const void*)&k_propagate<R, M3D, false, SHAPED, ENERGY>;
+    f[1] = (const void*)&k_propagate<R, M3D, true, SHAPED, ENERGY>;
+}
+
+template <typename R>
+static void model3d_variants(int shaped, int energy, const void** f)
+{
+    if (shaped && energy)
+        keyed_variants<R, true, true, true>(f);
+    else if (shaped)
+        keyed_variants<R, true, true, false>(f);
+    else if (energy)
+        keyed_variants<R, true, false, true>(f);
+    else
+        keyed_variants<R, true, false, false>(f);
+}
+
+hipError_t occupancy_propagate(int model, int prec, int block, int shaped, int energy,
+                               int* blocks_per_cu)
 {
     const void* f[2] = {nullptr, nullptr};
-    if (model == 1 && prec == 1 && shaped) {
-        f[0] = (const void*)&k_propagate<float, true, false, true>;
-        f[1] = (const void*)&k_propagate<float, true, true, true>;
-    } else if (model == 1 && prec == 1) {
-        f[0] = (const void*)&k_propagate<float, true, false, false>;
-        f[1] = (const void*)&k_propagate<float, true, true, false>;
-    } else if (model == 1 && prec == 0 && shaped) {
-        f[0] = (const void*)&k_propagate<double, true, false, true>;
-        f[1] = (const void*)&k_propagate<double, true, true, true>;
-    } else if (model == 1 && prec == 0) {
-        f[0] = (const void*)&k_propagate<double, true, false, false>;
-        f[1] = (const void*)&k_propagate<double, true, true, false>;
-    } else if (model == 0 && prec == 1) {
-        f[0] = (const void*)&k_propagate<float, false, false, false>;
-        f[1] = (const void*)&k_propagate<float, false, true, false>;
-    } else if (model == 0 && prec == 0) {
-        f[0] = (const void*)&k_propagate<double, false, false, false>;
-        f[1] = (const void*)&k_propagate<double, false, true, false>;
-    } else {
+    if (model == 1 && prec == 1)
+        model3d_variants<float>(shaped, energy, f);
+    else if (model == 1 && prec == 0)
+        model3d_variants<double>(shaped, energy, f);
+    else if (model == 0 && prec == 1)
+        keyed_variants<float, false, false, false>(f);
+    else if (model == 0 && prec == 0)
+        keyed_variants<double, false, false, false>(f);
+    else
         return hipErrorInvalidValue;
-    }
     // the smaller residency of the two key variants, so either fits the grid
     int lo = 1 << 30;
     for (const void* fn : f) {
@@ -794,6 +877,20 @@ __device__ __forceinline__ double lis_weight(const LisDev& L, double P)
     return L.norm * ::pow(P, -L.index) / (P * P);
 }
 
+// Energy form: U = 4 pi p^2 f / v is transported with the loss weight, so a
+// particle contributes beta0 / beta_ex J_LIS(P_ex) exp(-loss) to J_mod(P0).
+__device__ __forceinline__ double beta_of(const LisDev& L, double P)
+{
+    const double pc = L.abs_z * P;
+    return pc / ::sqrt(pc * pc + L.mass * L.mass);
+}
+
+__device__ __forceinline__ double energy_weight(const LisDev& L, double beta0, double P,
+                                                double loss)
+{
+    return beta0 / beta_of(L, P) * (L.norm * ::pow(P, -L.index)) * ::exp(-loss);
+}
+
 __global__ void __launch_bounds__(kReduceBlock) k_reduce(const ReduceArgs a)
 {
     __shared__ uint32_t hist[kNHist];
@@ -807,6 +904,7 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(const ReduceArgs a)
     double sw = 0.0, st = 0.0;
     unsigned long long sn = 0, ncap = 0, nnan = 0, nused = 0;
     const double inv_p0 = 1.0 / sg.P0;
+    const double beta0 = L.energy ? beta_of(L, sg.P0) : 0.0;
     for (uint32_t i = threadIdx.x; i < sg.count; i += kReduceBlock) {
         const uint32_t o = sg.out_offset + i;
         const uint32_t nf = a.exNF[o];
@@ -821,7 +919,7 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(const ReduceArgs a)
             continue;
         }
         const double P = a.exP[o];
-        sw += lis_weight(L, P);
+        sw += L.energy ? energy_weight(L, beta0, P, a.exL[o]) : lis_weight(L, P);
         st += a.exT[o];
         ++nused;
         int j = (int)::floor(128.0 * ::log10(P * inv_p0) / 3.0);
@@ -841,7 +939,9 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(const ReduceArgs a)
         for (uint32_t i = threadIdx.x; i < sg.count; i += kReduceBlock) {
             const uint32_t o = sg.out_offset + i;
             if ((a.exNF[o] >> kFlagShift) != 0u) continue;
-            const double dw = lis_weight(L, a.exP[o]) - mean;
+            const double w = L.energy ? energy_weight(L, beta0, a.exP[o], a.exL[o])
+                                      : lis_weight(L, a.exP[o]);
+            const double dw = w - mean;
             ss += dw * dw;
         }
     }
@@ -852,7 +952,9 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(const ReduceArgs a)
         for (int i = threadIdx.x; i < kNHist; i += kReduceBlock)
             a.hist[(size_t)ob * kNHist + i] = hist[i];
     if (threadIdx.x == 0) {
-        const double p2 = sg.P0 * sg.P0;
+        // momentum form: mean of f_LIS(P_ex) times P0^2; energy form: the mean
+        // contribution itself
+        const double p2 = L.energy ? 1.0 : sg.P0 * sg.P0;
         if (a.flux) a.flux[ob] = p2 * mean;
         if (a.flux_se) a.flux_se[ob] = NU > 1 ? p2 * ::sqrt(SS / (N - 1.0) / N) : 0.0;
         if (a.mean_t) a.mean_t[ob] = NU > 0 ? ST / N : 0.0;

@@ -69,6 +69,7 @@ struct JobCopy {
     uint32_t bin_offset = 0;
     uint64_t total = 0;
     std::vector<double> orbit;  // 3 per position
+    int formulation = 0;        // 0 momentum form, 1 energy form
 };
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
@@ -150,6 +151,9 @@ cosmica_status validate(const cosmica_job* j)
     }
     if (total >= (1ull << 32)) return COSMICA_EINVAL;
     if ((uint64_t)j->bin_offset + (uint64_t)j->n_bins > (1ull << 32)) return COSMICA_EINVAL;
+    // formulation: momentum (any model) or energy (3D)
+    if (j->formulation != 0 && j->formulation != 1) return COSMICA_EINVAL;
+    if (j->formulation == 1 && h.model != COSMICA_MODEL_3D) return COSMICA_EINVAL;
     // moving detection point: positions inside the heliopause
     if (j->n_orbit > COSMICA_MAX_ORBIT || (j->n_orbit > 0 && j->orbit == nullptr))
         return COSMICA_EINVAL;
@@ -184,6 +188,7 @@ JobCopy copy_job(const cosmica_job* j)
     c.bin_offset = j->bin_offset;
     for (uint32_t n : c.cnt) c.total += n;
     if (j->n_orbit > 0) c.orbit.assign(j->orbit, j->orbit + 3 * (size_t)j->n_orbit);
+    c.formulation = j->formulation;
     return c;
 }
 
@@ -216,6 +221,8 @@ void make_tables(const JobCopy& jc, JobDev<R>* J, RegionDev<R>* reg, LisDev* lis
     J->shaped = (hs || rb_nose != h.r_boundary_au) ? 1 : 0;
     J->n_orbit = (uint32_t)(jc.orbit.size() / 3);
     J->orbit_off = 0;  // set where the positions are placed
+    J->energy = jc.formulation == 1 ? 1 : 0;
+    J->mass = s.mass_gev;
     J->sin_tn = (R)std::sin(h.nose_theta_rad);
     J->cos_tn = (R)std::cos(h.nose_theta_rad);
     const double phn = std::fmod(h.nose_phi_rad, 2.0 * kPiH);
@@ -268,6 +275,9 @@ void make_tables(const JobCopy& jc, JobDev<R>* J, RegionDev<R>* reg, LisDev* lis
     }
     lis->norm = s.lis_norm;
     lis->index = s.lis_index;
+    lis->abs_z = std::fabs((double)s.charge);
+    lis->mass = s.mass_gev;
+    lis->energy = jc.formulation == 1 ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -385,10 +395,12 @@ void make_chunks(const std::vector<SegmentDev>& segs, const std::vector<uint32_t
 }
 
 int grid_for(cosmica_ctx* ctx, int model, int prec, const cosmica_launch& L, uint64_t lanes_wanted,
-             bool shaped)
+             bool shaped, bool energy)
 {
     int occ = 0;
-    if (occupancy_propagate(model, prec, L.block, shaped ? 1 : 0, &occ) != hipSuccess || occ < 1)
+    if (occupancy_propagate(model, prec, L.block, shaped ? 1 : 0, energy ? 1 : 0, &occ) !=
+            hipSuccess ||
+        occ < 1)
         occ = 1;
     int bpc = L.blocks_per_cu > 0 ? std::min(L.blocks_per_cu, occ) : occ;
     uint64_t grid = (uint64_t)ctx->num_cus * (uint64_t)bpc;
@@ -462,6 +474,8 @@ struct cosmica_plan {
     bool own_out = true;
     bool uniform_key = false;  // every job has the same seed
     bool shaped = false;       // some job has a squashed heliopause or a heliosheath
+    bool energy = false;       // some job is in the energy form
+    double* exL = nullptr;     // energy form: summed loss per particle
     uint64_t key = 0;
     explicit cosmica_plan(cosmica_ctx* c) : ctx(c), mem(c) {}
 };
@@ -541,9 +555,12 @@ cosmica_status execute_prop(cosmica_plan* p)
         a.leftover_count = p->counters_d + 4;
         a.uniform_key = p->uniform_key ? 1u : 0u;
         a.shaped = p->shaped ? 1u : 0u;
+        a.energy = p->energy ? 1u : 0u;
+        a.exL = p->exL;
         a.key_lo = (uint32_t)(p->key & 0xffffffffu);
         a.key_hi = (uint32_t)(p->key >> 32);
-        const int grid = grid_for(ctx, model, p->prec, L, p->model_particles[model], p->shaped);
+        const int grid =
+            grid_for(ctx, model, p->prec, L, p->model_particles[model], p->shaped, p->energy);
         ctx->timings.grid_blocks = grid;
         ctx->timings.block = L.block;
         HIP_TRY(launch_model<R>(model, a, grid, L.block, ctx->stream));
@@ -655,6 +672,7 @@ cosmica_status cosmica_plan_create(cosmica_ctx* ctx, const cosmica_job* jobs, in
     p->uniform_key = true;
     for (const JobCopy& jc : p->jobs) p->uniform_key &= jc.seed == p->key;
     for (const JobCopy& jc : p->jobs) p->shaped |= job_shaped(jc);
+    for (const JobCopy& jc : p->jobs) p->energy |= jc.formulation == 1;
     cosmica_status st = precision == COSMICA_PREC_MIXED ? upload_tables<float>(p.get())
                                                          : upload_tables<double>(p.get());
     if (st != COSMICA_OK) return st;
@@ -668,6 +686,7 @@ cosmica_status cosmica_plan_create(cosmica_ctx* ctx, const cosmica_job* jobs, in
     if ((st = p->mem.alloc(&p->exP, total)) != COSMICA_OK) return st;
     if ((st = p->mem.alloc(&p->exT, total)) != COSMICA_OK) return st;
     if ((st = p->mem.alloc(&p->exNF, total)) != COSMICA_OK) return st;
+    if (p->energy && (st = p->mem.alloc(&p->exL, total)) != COSMICA_OK) return st;
     if (p->want_exits) {
         if ((st = p->mem.alloc(&p->exR, total)) != COSMICA_OK) return st;
         if ((st = p->mem.alloc(&p->exTh, total)) != COSMICA_OK) return st;
@@ -710,6 +729,7 @@ cosmica_status cosmica_plan_execute(cosmica_plan* p, const cosmica_bins_dev* out
     r.exP = p->exP;
     r.exT = p->exT;
     r.exNF = p->exNF;
+    r.exL = p->exL;
     r.seg_base = 0;
     r.out_base = 0;
     if (out == nullptr) {
@@ -787,7 +807,7 @@ cosmica_status cosmica_plan_read(cosmica_plan* p, cosmica_result* results)
     bool capped = false;
     bool need_exits = false;
     for (size_t j = 0; j < p->jobs.size(); ++j) need_exits |= results[j].exits != nullptr;
-    std::vector<double> eP, eT, eR, eTh, ePh;
+    std::vector<double> eP, eT, eR, eTh, ePh, eL;
     std::vector<uint32_t> eNF;
     if (need_exits) {
         const size_t n = p->total_particles;
@@ -797,6 +817,10 @@ cosmica_status cosmica_plan_read(cosmica_plan* p, cosmica_result* results)
         HIP_TRY(hipMemcpy(eP.data(), p->exP, n * 8, hipMemcpyDeviceToHost));
         HIP_TRY(hipMemcpy(eT.data(), p->exT, n * 8, hipMemcpyDeviceToHost));
         HIP_TRY(hipMemcpy(eNF.data(), p->exNF, n * 4, hipMemcpyDeviceToHost));
+        if (p->exL) {
+            eL.resize(n);
+            HIP_TRY(hipMemcpy(eL.data(), p->exL, n * 8, hipMemcpyDeviceToHost));
+        }
         if (p->want_exits) {
             eR.resize(n);
             eTh.resize(n);
@@ -833,6 +857,7 @@ cosmica_status cosmica_plan_read(cosmica_plan* p, cosmica_result* results)
                 e.r = p->want_exits ? eR[o] : 0.0;
                 e.theta = p->want_exits ? eTh[o] : 0.0;
                 e.phi = p->want_exits ? ePh[o] : 0.0;
+                e.loss = p->jobs[j].formulation == 1 ? eL[o] : 0.0;
             }
         }
     }
@@ -1204,10 +1229,13 @@ cosmica_status sweep(cosmica_ctx* ctx, const cosmica_job* jobs, int n_jobs, int 
         if ((st = consider(cosmica_launch{blk, 0, best.chunk, best.order})) != COSMICA_OK) break;
     if (st == COSMICA_OK) {
         int occ = 0;
-        bool shaped_jobs = false;
-        for (int j = 0; j < n_jobs; ++j) shaped_jobs |= job_shaped(copy_job(&jobs[j]));
-        if (occupancy_propagate(model, precision, best.block, shaped_jobs ? 1 : 0, &occ) !=
-                hipSuccess ||
+        bool shaped_jobs = false, energy_jobs = false;
+        for (int j = 0; j < n_jobs; ++j) {
+            shaped_jobs |= job_shaped(copy_job(&jobs[j]));
+            energy_jobs |= jobs[j].formulation == 1;
+        }
+        if (occupancy_propagate(model, precision, best.block, shaped_jobs ? 1 : 0,
+                                energy_jobs ? 1 : 0, &occ) != hipSuccess ||
             occ < 1)
             occ = 1;
         const cosmica_launch base = best;
@@ -1325,6 +1353,7 @@ struct ServeGroup {
     uint32_t chunks_cap = 0;
     void* chunks_block = nullptr;
     uint64_t pool_cap = 0;
+    double* exL = nullptr;  // energy form: allocated when the first energy-form request arrives
     double* exP = nullptr;
     double* exT = nullptr;
     uint32_t* exNF = nullptr;
@@ -1348,7 +1377,8 @@ struct ServeGroup {
     std::vector<ChunkDev> carry;               // chunks to hand to the next slice
     std::vector<Req*> resident;
     std::vector<Req*> releasing;               // cancelled, freed after the next slice
-    int grid = 0, grid_shaped = 0, block = 256;
+    int grid = 0, block = 256;
+    int grid_var[4] = {0, 0, 0, 0};  // by (shaped | 2 energy)
     uint32_t n_chunks_last = 0;
     explicit ServeGroup(cosmica_ctx* c) : ctx(c), mem(c) {}
 };
@@ -1404,10 +1434,12 @@ cosmica_status group_create(cosmica_ctx* ctx, int model, int prec, ServeGroup** 
     if ((st = g->mem.alloc(&g->segs_d, (size_t)S * B)) != COSMICA_OK) return st;
     const cosmica_launch& L = ctx->launch[model][prec];
     g->block = L.block;
-    g->grid = grid_for(ctx, model, prec, L, ~0ull >> 8, false);
-    // slices with a squashed heliosphere run the kernel that tests it; the
-    // parking arrays are sized for the larger grid
-    g->grid_shaped = std::min(g->grid, grid_for(ctx, model, prec, L, ~0ull >> 8, true));
+    g->grid = grid_for(ctx, model, prec, L, ~0ull >> 8, false, false);
+    // slices with a squashed heliosphere or the energy form run the kernel
+    // variants for them; the parking arrays are sized for the largest grid
+    for (int v = 1; v < 4; ++v)
+        g->grid_var[v] = std::min(g->grid, grid_for(ctx, model, prec, L, ~0ull >> 8, v & 1, v & 2));
+    g->grid_var[0] = g->grid;
     g->susp_cap = (uint32_t)g->grid * (uint32_t)g->block;
     if ((st = g->mem.alloc(&g->susp[0], g->susp_cap)) != COSMICA_OK) return st;
     if ((st = g->mem.alloc(&g->susp[1], g->susp_cap)) != COSMICA_OK) return st;
@@ -1523,6 +1555,16 @@ cosmica_status admit(cosmica_ctx* ctx)
             ctx->cv.notify_all();
             continue;
         }
+        if (q->job.formulation == 1 && g->exL == nullptr) {
+            cosmica_status st = g->mem.alloc(&g->exL, g->pool_cap);
+            if (st != COSMICA_OK) {  // no room for the energy form's loss records
+                ctx->queued.pop_front();
+                q->state = 2;
+                q->status = st;
+                ctx->cv.notify_all();
+                continue;
+            }
+        }
         if (!pool_take(g, q->job.total, &off)) break;
         ctx->queued.pop_front();
         q->slot = g->free_slots.back();
@@ -1604,8 +1646,12 @@ cosmica_status launch_slice(ServeGroup* g)
     // every request holding a slot may have particles in this slice
     for (const Req* q : g->resident) a.shaped |= job_shaped(q->job) ? 1u : 0u;
     for (const Req* q : g->releasing) a.shaped |= job_shaped(q->job) ? 1u : 0u;
+    for (const Req* q : g->resident) a.energy |= q->job.formulation == 1 ? 1u : 0u;
+    for (const Req* q : g->releasing) a.energy |= q->job.formulation == 1 ? 1u : 0u;
+    a.exL = g->exL;
     g->n_chunks_last = nch;
-    HIP_TRY(launch_model<R>(g->model, a, a.shaped ? g->grid_shaped : g->grid, g->block, s));
+    HIP_TRY(launch_model<R>(g->model, a, g->grid_var[(a.shaped ? 1 : 0) | (a.energy ? 2 : 0)],
+                            g->block, s));
     // the host copy of the chunk list must outlive the asynchronous upload
     HIP_TRY(hipStreamSynchronize(s));
     return COSMICA_OK;
@@ -1646,6 +1692,7 @@ cosmica_status finish_request(ServeGroup* g, Req* q)
     r.exP = g->exP;
     r.exT = g->exT;
     r.exNF = g->exNF;
+    r.exL = g->exL;
     r.seg_base = (uint32_t)q->slot * ServeGroup::kBinsPerSlot;
     r.out_base = 0;
     r.hist = g->r_hist;
@@ -1669,15 +1716,18 @@ cosmica_status finish_request(ServeGroup* g, Req* q)
     if (R.n_nan) HIP_TRY(hipMemcpy(R.n_nan, g->r_nnan, nb * 4, hipMemcpyDeviceToHost));
     if (R.exits) {
         const size_t n = q->job.total;
-        std::vector<double> P(n), T(n);
+        std::vector<double> P(n), T(n), Ls(n, 0.0);
         std::vector<uint32_t> NF(n);
         HIP_TRY(hipMemcpy(P.data(), g->exP + q->ex0, n * 8, hipMemcpyDeviceToHost));
         HIP_TRY(hipMemcpy(T.data(), g->exT + q->ex0, n * 8, hipMemcpyDeviceToHost));
         HIP_TRY(hipMemcpy(NF.data(), g->exNF + q->ex0, n * 4, hipMemcpyDeviceToHost));
+        if (q->job.formulation == 1)
+            HIP_TRY(hipMemcpy(Ls.data(), g->exL + q->ex0, n * 8, hipMemcpyDeviceToHost));
         for (size_t i = 0; i < n; ++i) {
             cosmica_exit& e = R.exits[i];
             e.P = P[i];
             e.t = T[i];
+            e.loss = Ls[i];
             e.r = e.theta = e.phi = 0.0;
             e.n = NF[i] & ((1u << kFlagShift) - 1u);
             e.flags = NF[i] >> kFlagShift;

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_function():
 
 def test_abi_version_and_strerror():
     lib = C.load()
-    assert lib.cosmica_abi_version() == 3
+    assert lib.cosmica_abi_version() == 4
     for st in (C.OK, C.EINVAL, C.ENOMEM, C.EDEVICE, C.EBUSY, C.ECANCELED, C.ESTEPCAP,
                C.ENOTFOUND, 123):
         assert isinstance(lib.cosmica_strerror(st), bytes)
@@ -185,6 +185,13 @@ def test_orbit_positions_are_checked():
     tail = [130.0, math.pi - h["nose_theta_rad"], h["nose_phi_rad"] + math.pi]
     assert C.validate_job(W.with_orbit(hs, [tail])) == C.OK
     assert C.validate_job(W.with_orbit(hs, [nose])) == C.EINVAL
+
+
+def test_formulation_is_checked():
+    job = W.c2_job(particles_per_bin=10, n_bins=4)
+    for f, want in ((0, C.OK), (1, C.OK), (2, C.EINVAL), (-1, C.EINVAL)):
+        assert C.validate_job(dict(job, formulation=f)) == want, f
+    assert C.validate_job(dict(W.c1_job(), formulation=1)) == C.EINVAL  # energy form: 3D only
 
 
 def test_bins_and_counts_are_checked():

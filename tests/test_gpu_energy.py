@@ -1,0 +1,132 @@
+"""The energy form of the transport equation (Eq.(1)) on the GPU, against the oracle.
+
+cosmica_job.formulation = 1 integrates the kinetic energy with the loss term
+of Eq.(2) and weights each exit by beta0/beta_ex J_LIS(P_ex) exp(-loss)
+(Eq.(4)); the paper's Versions 0-3 used this form before Version 6 moved to
+the momentum form (Sec. VI).  The integrator's own device code runs in every
+test:
+
+* FP64 particle by particle against the oracle: the spherical 3D tolerances
+  for step counts and flux, and each identical path's summed loss to 1e-9;
+* mixed precision with the paired test;
+* energy- and momentum-form spectra from the GPU agree within the Monte Carlo
+  error (the paper's version comparison, Sec. VIII);
+* a momentum-form job in a launch that also carries the energy form is bitwise
+  unchanged; served energy-form jobs equal batch ones.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2502_06319_amd import cosmica as C
+from tests.test_gpu_path import _compare_3d, _split
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("hist", "flux", "flux_se", "mean_exit_time_s", "steps", "n_capped", "n_nan")
+
+
+def _energy_job(W, n, bins, **kw):
+    job = W.c2_job(particles_per_bin=n, n_bins=bins, **kw)
+    job["formulation"] = 1
+    return job
+
+
+def test_energy_form_fp64_path_by_path_without_the_sheet(eng, orc, W, othreads):
+    """Without the current sheet, FP64 energy-form paths coincide with the
+    oracle's: identical step counts, exit rigidities and summed losses."""
+    job = _energy_job(W, 400, 8)
+    job["helio"]["hcs"] = 0
+    g = eng.run(job, "fp64", exits=True)[0]
+    o = orc.run_job(job, threads=othreads)
+    for b, (ge, r) in enumerate(zip(_split(job, g["exits"]), o)):
+        oe = r["records"]
+        m = ge["n"] == oe["n"]
+        assert m.mean() >= 0.99
+        np.testing.assert_allclose(ge["loss"][m], oe["loss"][m], rtol=1e-9)
+        np.testing.assert_allclose(ge["P"][m], oe["P"][m], rtol=1e-9)
+        assert np.all(ge["loss"] > 0)
+        assert g["flux"][b] == pytest.approx(r["flux"], rel=1e-6)
+
+
+def test_energy_form_fp64_against_oracle(eng, orc, W, othreads):
+    """With the current sheet, rounding differences grow along sheet-riding
+    paths (as in the momentum form), so the spherical 3D tolerances apply."""
+    job = _energy_job(W, 400, 8)
+    overall, stats = _compare_3d(eng, orc, job, "fp64", othreads, "energy-fp64")
+    assert overall >= 0.90
+    for same, dJ, se_pair, r in stats:
+        assert same >= 0.75
+        assert abs(dJ) <= 0.5 * r["flux_se"]
+    g = eng.run(job, "fp64", exits=True)[0]
+    o = orc.run_job(job, threads=othreads)
+    close = []
+    for ge, r in zip(_split(job, g["exits"]), o):
+        oe = r["records"]
+        m = ge["n"] == oe["n"]
+        close.append(np.mean(np.abs(ge["loss"][m] / oe["loss"][m] - 1.0) < 1e-9))
+    assert np.mean(close) >= 0.9
+
+
+def test_energy_form_mixed_against_oracle(eng, orc, W, othreads):
+    job = _energy_job(W, 1000, 8)
+    overall, stats = _compare_3d(eng, orc, job, "mixed", othreads, "energy-mixed")
+    for same, dJ, se_pair, r in stats:
+        N = r["n_used"]
+        assert abs(dJ) <= 4.0 * se_pair + 1e-12 * r["flux"]
+        assert abs(dJ) <= max(r["flux_se"], r["flux"] / math.sqrt(N))
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_energy_and_momentum_forms_agree(eng, W, precision):
+    e_job = _energy_job(W, 1500, 8)
+    m_job = dict(e_job, formulation=0)
+    e = eng.run(e_job, precision)[0]
+    m = eng.run(m_job, precision)[0]
+    for b in range(8):
+        assert abs(e["flux"][b] - m["flux"][b]) <= 2.0 * math.hypot(e["flux_se"][b], m["flux_se"][b])
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_momentum_job_unchanged_beside_the_energy_form(eng, W, precision):
+    mom = W.c2_job(particles_per_bin=300, n_bins=5)
+    en = _energy_job(W, 100, 3)
+    en["job_tag"] = 6
+    alone = eng.run(mom, precision, exits=True)[0]
+    both = eng.run([en, mom], precision, exits=True)
+    for k in KEYS:
+        np.testing.assert_array_equal(both[1][k], alone[k], err_msg=k)
+    np.testing.assert_array_equal(both[1]["exits"], alone["exits"])
+    assert np.all(alone["exits"]["loss"] == 0.0)
+    assert np.all(both[0]["exits"]["loss"] > 0.0)
+
+
+def test_energy_form_is_3d_only(eng, W):
+    job = W.c1_job(particles_per_bin=8)
+    job["formulation"] = 1
+    assert C.validate_job(job) == C.EINVAL
+
+
+def test_served_energy_form_equals_batch(W):
+    old = os.environ.get("COSMICA_SLICE_STEPS")
+    os.environ["COSMICA_SLICE_STEPS"] = "300"
+    try:
+        jobs = [_energy_job(W, 150, 3), W.c2_job(particles_per_bin=150, n_bins=3)]
+        jobs[1]["job_tag"] = 11
+        with C.Engine(0) as e:
+            tickets = [e.submit(j, "mixed", exits=True) for j in jobs]
+            for t in tickets:
+                assert t.wait(120000) == C.OK
+            for j, t in zip(jobs, tickets):
+                alone = e.run(j, "mixed", exits=True)[0]
+                got = t.result()
+                for k in KEYS:
+                    np.testing.assert_array_equal(got[k], alone[k], err_msg=k)
+                np.testing.assert_array_equal(got["exits"]["loss"], alone["exits"]["loss"])
+    finally:
+        if old is None:
+            del os.environ["COSMICA_SLICE_STEPS"]
+        else:
+            os.environ["COSMICA_SLICE_STEPS"] = old

@@ -47,12 +47,23 @@ def _split(job, exits):
     return out
 
 
-def _paired(ge, oe, P0):
-    w_g, w_o = _weights(ge["P"]), _weights(oe["P"])
-    d = w_g - w_o
+def _contributions(ex, P0, job=None):
+    """Each exit's contribution to J_mod(P0): P0^2 J_LIS(P_ex)/P_ex^2 in the
+    momentum form; beta0/beta_ex J_LIS(P_ex) exp(-loss) in the energy form."""
+    if job is None or job.get("formulation", 0) == 0:
+        return P0 * P0 * _weights(ex["P"])
+    sp = job["species"]
+    Z, M = abs(sp["charge"]), sp["mass_gev"]
+    beta = lambda P: Z * P / np.sqrt((Z * P) ** 2 + M * M)
+    return beta(P0) / beta(ex["P"]) * sp["lis_norm"] * ex["P"] ** (-sp["lis_index"]) * np.exp(
+        -ex["loss"])
+
+
+def _paired(ge, oe, P0, job=None):
+    d = _contributions(ge, P0, job) - _contributions(oe, P0, job)
     N = len(d)
-    dJ = P0 * P0 * d.mean()
-    se_pair = P0 * P0 * d.std(ddof=1) / math.sqrt(N) if N > 1 else 0.0
+    dJ = d.mean()
+    se_pair = d.std(ddof=1) / math.sqrt(N) if N > 1 else 0.0
     return dJ, se_pair
 
 
@@ -101,7 +112,7 @@ def _compare_3d(eng, orc, job, precision, othreads, tag):
         N = len(oe)
         same = np.mean(ge["n"] == oe["n"])
         tot_same += same * N
-        dJ, se_pair = _paired(ge, oe, r["P0"])
+        dJ, se_pair = _paired(ge, oe, r["P0"], job)
         assert dJ == pytest.approx(g["flux"][b] - r["flux"], rel=1e-6, abs=1e-12 * r["flux"])
         _report(tag, b, r, g["flux"][b], same, dJ, se_pair)
         assert int(g["hist"][b].sum()) == N
