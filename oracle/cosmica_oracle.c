@@ -661,3 +661,52 @@ void orc_reduce_bin(const orc_params* p, double P0_gv, const orc_exit* rec, uint
         }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Re-weighting with tabulated spectra: ln J linear in ln P between knots,   */
+/* end segments extended.                                                     */
+/* ------------------------------------------------------------------------ */
+static double table_lis(uint32_t n_knots, double lnP0, double dlnP, const double* lnJ,
+                        double P)
+{
+    double x = (log(P) - lnP0) / dlnP;
+    int k = (int)floor(x);
+    if (k < 0) k = 0;
+    if (k > (int)n_knots - 2) k = (int)n_knots - 2;
+    double f = x - (double)k;
+    return exp(lnJ[k] + f * (lnJ[k + 1] - lnJ[k]));
+}
+
+void orc_reweight_bin(const orc_params* p, double P0_gv, const orc_exit* rec, uint32_t n,
+                      uint32_t n_lis, uint32_t n_knots, double lnP0, double dlnP,
+                      const double* lnJ, double* flux, double* flux_se)
+{
+    derived d;
+    if (derive(p, &d) != 0 || n_knots < 2) return;
+    const double b0 = beta_of(&d, P0_gv);
+    for (uint32_t l = 0; l < n_lis; ++l) {
+        const double* t = lnJ + (size_t)l * n_knots;
+        double sw = 0.0;
+        uint32_t used = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+            if (rec[i].flags & (ORC_FLAG_CAPPED | ORC_FLAG_NAN)) continue;
+            double P = rec[i].P, J = table_lis(n_knots, lnP0, dlnP, t, P);
+            sw += p->formulation == 1 ? b0 / beta_of(&d, P) * J * exp(-rec[i].loss)
+                                      : P0_gv * P0_gv * (J / (P * P));
+            used++;
+        }
+        flux[l] = used ? sw / (double)used : 0.0;
+        flux_se[l] = 0.0;
+        if (used > 1) {
+            double mean = sw / (double)used, ss = 0.0;
+            for (uint32_t i = 0; i < n; ++i) {
+                if (rec[i].flags & (ORC_FLAG_CAPPED | ORC_FLAG_NAN)) continue;
+                double P = rec[i].P, J = table_lis(n_knots, lnP0, dlnP, t, P);
+                double w = p->formulation == 1 ? b0 / beta_of(&d, P) * J * exp(-rec[i].loss)
+                                               : P0_gv * P0_gv * (J / (P * P));
+                ss += (w - mean) * (w - mean);
+            }
+            flux_se[l] = sqrt(ss / ((double)used - 1.0) / (double)used);
+        }
+    }
+}

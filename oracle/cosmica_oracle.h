@@ -175,6 +175,18 @@ void orc_reduce_bin(const orc_params* p, double P0_gv, const orc_exit* rec, uint
 /* J_LIS of the parameters at rigidity P [GV]. */
 double orc_lis(const orc_params* p, double P_gv);
 
+/* Re-weighting of stored exit records with other local interstellar spectra
+ * (the weight of Eq.(4) with another LIS; the paths do not depend on it).
+ * Each of n_lis spectra is tabulated as ln J at n_knots points
+ * ln P = lnP0 + k dlnP; between knots ln J is linear in ln P and beyond the
+ * ends the end segments are extended (READING: the format of tabulated LIS
+ * such as Galprop's, interpolated in log-log).  lnJ[l * n_knots + k];
+ * flux[l], flux_se[l] receive the bin's J_mod(P0) and its standard error for
+ * spectrum l (momentum or energy form as p->formulation). */
+void orc_reweight_bin(const orc_params* p, double P0_gv, const orc_exit* rec, uint32_t n,
+                      uint32_t n_lis, uint32_t n_knots, double lnP0, double dlnP,
+                      const double* lnJ, double* flux, double* flux_se);
+
 #ifdef __cplusplus
 }
 #endif

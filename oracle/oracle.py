@@ -139,6 +139,10 @@ def lib():
         L.orc_locate.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, ctypes.POINTER(ctypes.c_int32)]
         L.orc_locate.restype = ctypes.c_int
+        L.orc_reweight_bin.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_double,
+                                       ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                       ctypes.c_uint32, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.orc_lis.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_double]
         L.orc_lis.restype = ctypes.c_double
         _lib = L
@@ -267,6 +271,19 @@ def locate(p: OrcParams, r: float, theta: float, phi: float) -> tuple[bool, int]
     if out < 0:
         raise ValueError("oracle rejected the parameters")
     return bool(out), int(k.value)
+
+
+def reweight_bin(p: OrcParams, P0: float, rec: np.ndarray, lnP0: float, dlnP: float,
+                 lnJ: np.ndarray):
+    """J_mod(P0) and its standard error for each tabulated spectrum (rows of lnJ)."""
+    rec = np.ascontiguousarray(rec, dtype=EXIT_DTYPE)
+    lnJ = np.ascontiguousarray(np.atleast_2d(lnJ), dtype=np.float64)
+    n_lis, n_knots = lnJ.shape
+    flux = np.zeros(n_lis)
+    se = np.zeros(n_lis)
+    lib().orc_reweight_bin(ctypes.byref(p), P0, rec.ctypes.data, len(rec), n_lis, n_knots,
+                           lnP0, dlnP, lnJ.ctypes.data, flux.ctypes.data, se.ctypes.data)
+    return flux, se
 
 
 def lis(p: OrcParams, P: float) -> float:

@@ -6,8 +6,9 @@ of Eq.(2) and weights each exit by beta0/beta_ex J_LIS(P_ex) exp(-loss)
 the momentum form (Sec. VI).  The integrator's own device code runs in every
 test:
 
-* FP64 particle by particle against the oracle: the spherical 3D tolerances
-  for step counts and flux, and each identical path's summed loss to 1e-9;
+* FP64 against the oracle: without the current sheet particle by particle
+  (step counts, exit rigidities and summed losses to 1e-9); with it the
+  spherical 3D tolerances, since sheet-riding paths amplify rounding;
 * mixed precision with the paired test;
 * energy- and momentum-form spectra from the GPU agree within the Monte Carlo
   error (the paper's version comparison, Sec. VIII);
