@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 from paper_2502_06319_amd import cosmica as C  # noqa: E402
+from paper_2502_06319_amd import scan as S  # noqa: E402
 from paper_2502_06319_amd import workloads as W  # noqa: E402
 
 TUNE_CACHE = os.path.join(ROOT, "paper_2502_06319_amd", "tuned_launch.txt")
@@ -236,6 +237,26 @@ def energy_form_leg(eng, sync, momentum_rate) -> dict:
             "momentum_over_energy": round(momentum_rate / rate, 3)}
 
 
+def reweight_leg(plan, n_particles, pass_ms) -> dict:
+    """Re-weighting of the batched pass's stored exits with 64 local
+    interstellar spectra (power laws over a grid of index and normalisation,
+    one ln J table each): the fitting use, where one propagation serves every
+    spectrum.  Timed per call, tables up and fluxes down included."""
+    lnJ, lnP0, dlnP = S.power_law_tables(np.geomspace(1.2e4, 2.8e4, 4),
+                                         np.linspace(2.4, 3.2, 16), n_knots=48)
+    plan.reweight(lnP0, dlnP, lnJ)  # warm
+    t = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        plan.reweight(lnP0, dlnP, lnJ)
+        t.append(time.perf_counter() - t0)
+    ms = float(np.median(t)) * 1e3
+    return {"workload": f"{len(lnJ)} tabulated spectra over the batched pass's exits",
+            "n_lis": len(lnJ), "ms_per_call": round(ms, 3),
+            "exit_weights_per_s": float(n_particles * len(lnJ) / (ms * 1e-3)),
+            "propagation_pass_over_reweight": round(pass_ms / ms, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +270,7 @@ def main():
     ap.add_argument("--no-heliosheath", action="store_true")
     ap.add_argument("--no-orbit", action="store_true")
     ap.add_argument("--no-energy", action="store_true")
+    ap.add_argument("--no-reweight", action="store_true")
     ap.add_argument("--heliosheath-only", action="store_true",
                     help="time only the heliosheath workload (for profiling)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -259,7 +281,7 @@ def main():
     args = ap.parse_args()
     if args.batched_only or args.heliosheath_only:
         args.no_plain = args.no_serve = args.no_cpu = True
-        args.no_heliosheath = args.no_orbit = args.no_energy = True
+        args.no_heliosheath = args.no_orbit = args.no_energy = args.no_reweight = True
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the quasi-particles are "
               "independent, and a run over several GPUs would give each one whole bins (bin_offset).",
@@ -300,6 +322,9 @@ def main():
     log(f"mixed: {value:.4e} steps/s, {ms_per_step:.1f} ms per pass, propagate {prop_avg:.1f} ms")
     res = plan.read()
     assert sum(int(r["n_nan"].sum()) for r in res) == 0
+    reweight = None if args.no_reweight else reweight_leg(plan, n_particles, ms_per_step)
+    if reweight:
+        log("reweight:", reweight)
     plan.destroy()
 
     ops = sum(OPS_PER_STEP["3d"].values())
@@ -363,7 +388,7 @@ def main():
                    "launch": launch["mixed"], "parallelism": "1 GPU"},
         "spectra_per_hour": round(spectra_per_hour, 1),
         "plain_fp64": plain, "energy_form": energy, "heliosheath": helio, "orbit": orbit,
-        "serving": serving,
+        "reweight": reweight, "serving": serving,
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

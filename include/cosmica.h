@@ -261,6 +261,23 @@ cosmica_status cosmica_plan_read(cosmica_plan* plan, cosmica_result* results);
 cosmica_status cosmica_plan_info(const cosmica_plan* plan, uint64_t* total_bins,
                                  uint64_t* total_particles, int32_t* n_jobs);
 
+/* Re-weights the exit records of the plan's last execution with n_lis other
+ * local interstellar spectra: the paths do not depend on the spectrum, which
+ * only enters the weight of Eq.(4) (the parameter-fitting use of Sec. VIII).
+ * Each spectrum is tabulated as ln J at n_knots points ln P = lnP0 + k dlnP
+ * (P in GV); ln J is linear in ln P between knots and the end segments are
+ * extended.  lnJ: host, n_lis * n_knots (spectrum-major).  flux, flux_se: host,
+ * n_lis * total_bins, [l * total_bins + b] with bins in plan order (either may
+ * be NULL): J_mod(P0) and its standard error for spectrum l, in each job's
+ * formulation.  EINVAL if the plan has not been executed, n_lis is outside
+ * 1..COSMICA_MAX_REWEIGHT, n_knots outside 2..COSMICA_MAX_LIS_KNOTS, dlnP <= 0
+ * or a table value is not finite. */
+#define COSMICA_MAX_REWEIGHT 4096
+#define COSMICA_MAX_LIS_KNOTS 256
+cosmica_status cosmica_plan_reweight(cosmica_plan* plan, uint32_t n_lis, uint32_t n_knots,
+                                     double lnP0, double dlnP, const double* lnJ, double* flux,
+                                     double* flux_se);
+
 void cosmica_plan_destroy(cosmica_plan* plan);
 
 /* Launch shape used for (model, precision); the defaults come from the

@@ -129,6 +129,9 @@ _SIGS = {
     "cosmica_plan_info": (ctypes.c_int, [ctypes.c_void_p, c_u64_p, c_u64_p,
                                          ctypes.POINTER(ctypes.c_int32)]),
     "cosmica_plan_destroy": (None, [ctypes.c_void_p]),
+    "cosmica_plan_reweight": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                             ctypes.c_double, ctypes.c_double, c_double_p,
+                                             c_double_p, c_double_p]),
     "cosmica_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                           ctypes.POINTER(Launch)]),
     "cosmica_get_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
@@ -287,6 +290,21 @@ class Plan:
         self.last_status = _check(load().cosmica_plan_read(self.handle, arr), "plan_read",
                                   ok=(OK, ESTEPCAP))
         return [r.as_dict() for r in res]
+
+    def reweight(self, lnP0: float, dlnP: float, lnJ) -> tuple[np.ndarray, np.ndarray]:
+        """J_mod and its standard error for each tabulated spectrum (rows of
+        lnJ: ln J at ln P = lnP0 + k dlnP) from the last execution's exits:
+        arrays (n_lis, total_bins), bins in plan order."""
+        lnJ = np.ascontiguousarray(np.atleast_2d(lnJ), dtype=np.float64)
+        n_lis, n_knots = lnJ.shape
+        nb = self.info()["bins"]
+        flux = np.zeros((n_lis, nb))
+        se = np.zeros((n_lis, nb))
+        _check(load().cosmica_plan_reweight(self.handle, n_lis, n_knots, lnP0, dlnP,
+                                            lnJ.ctypes.data_as(c_double_p),
+                                            flux.ctypes.data_as(c_double_p),
+                                            se.ctypes.data_as(c_double_p)), "plan_reweight")
+        return flux, se
 
     def destroy(self):
         if self.handle:

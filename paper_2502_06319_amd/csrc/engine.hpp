@@ -142,6 +142,23 @@ struct ReduceArgs {
     uint32_t out_base;  // output index of segment seg_base
 };
 
+// Re-weighting of exit records with tabulated spectra.
+constexpr int kReweightGroup = 16;  // spectra per workgroup
+constexpr int kMaxLisKnots = 256;
+struct ReweightArgs {
+    const SegmentDev* segs;
+    const LisDev* lis;
+    const double* exP;
+    const uint32_t* exNF;
+    const double* exL;  // energy form (may be null without energy-form jobs)
+    const double* lnJ;  // n_lis * n_knots
+    uint32_t n_lis, n_knots;
+    double lnP0, dlnP;
+    uint32_t seg_base, out_base, total_bins, pad0;
+    double* flux;       // n_lis * total_bins
+    double* flux_se;
+};
+
 // Launchers (kernels.hip).
 hipError_t launch_propagate_3d_mixed(const PropArgs<float>& a, int grid, int block, hipStream_t s);
 hipError_t launch_propagate_3d_fp64(const PropArgs<double>& a, int grid, int block, hipStream_t s);
@@ -150,6 +167,7 @@ hipError_t launch_propagate_1d_fp64(const PropArgs<double>& a, int grid, int blo
 hipError_t occupancy_propagate(int model, int prec, int block, int shaped, int energy,
                                int* blocks_per_cu);
 hipError_t launch_reduce(const ReduceArgs& a, uint32_t n_segs, hipStream_t s);
+hipError_t launch_reweight(const ReweightArgs& a, uint32_t n_segs, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint32_t n, hipStream_t s);
 
 // Diagnostics: raw Philox words and normals for counters (i, c1, c2, c3),

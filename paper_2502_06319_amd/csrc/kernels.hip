@@ -971,6 +971,103 @@ hipError_t launch_reduce(const ReduceArgs& a, uint32_t n_segs, hipStream_t s)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Re-weighting of stored exit records with tabulated spectra (Eq.(4) with
+// other J_LIS): one workgroup per (segment, group of kReweightGroup spectra).
+// ln J is linear in ln P between knots ln P = lnP0 + k dlnP, with the end
+// segments extended.  The group's tables sit in LDS; each particle's ln P and
+// its form-dependent factor are computed once for the whole group.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kReduceBlock) k_reweight(const ReweightArgs a)
+{
+    __shared__ double tab[kReweightGroup * kMaxLisKnots];
+    __shared__ double shd[kReduceBlock / 64];
+    const uint32_t sidx = a.seg_base + blockIdx.x;
+    const uint32_t l0 = blockIdx.y * kReweightGroup;
+    const uint32_t nl = a.n_lis - l0 < (uint32_t)kReweightGroup ? a.n_lis - l0
+                                                                 : (uint32_t)kReweightGroup;
+    for (uint32_t i = threadIdx.x; i < nl * a.n_knots; i += kReduceBlock)
+        tab[i] = a.lnJ[(size_t)l0 * a.n_knots + i];
+    __syncthreads();
+    const SegmentDev sg = a.segs[sidx];
+    const LisDev L = a.lis[sg.job];
+    const double beta0 = L.energy ? beta_of(L, sg.P0) : 0.0;
+    const double p02 = sg.P0 * sg.P0;
+    const double inv_d = 1.0 / a.dlnP;
+    const int kmax = (int)a.n_knots - 2;
+    // weight of particle o with table t (the factor is beta0/beta_ex exp(-loss)
+    // in the energy form, P0^2/P_ex^2 in the momentum form)
+    auto factor_and_pos = [&](uint32_t o, double* fac, int* k, double* f) {
+        const double P = a.exP[o];
+        *fac = L.energy ? beta0 / beta_of(L, P) * ::exp(-a.exL[o]) : p02 / (P * P);
+        const double x = (::log(P) - a.lnP0) * inv_d;
+        // clamp before the conversion; beyond the ends f extrapolates
+        const double xc = x < 0.0 ? 0.0 : (x > (double)kmax ? (double)kmax : x);
+        const int kk = (int)::floor(xc);
+        *k = kk;
+        *f = x - (double)kk;
+    };
+    double acc[kReweightGroup];
+    for (int l = 0; l < kReweightGroup; ++l) acc[l] = 0.0;
+    unsigned long long nused = 0;
+    for (uint32_t i = threadIdx.x; i < sg.count; i += kReduceBlock) {
+        const uint32_t o = sg.out_offset + i;
+        if ((a.exNF[o] >> kFlagShift) != 0u) continue;  // capped or non-finite
+        double fac, f;
+        int k;
+        factor_and_pos(o, &fac, &k, &f);
+        ++nused;
+#pragma unroll
+        for (int l = 0; l < kReweightGroup; ++l) {
+            if ((uint32_t)l < nl) {
+                const double* t = tab + l * a.n_knots;
+                acc[l] += fac * ::exp(t[k] + f * (t[k + 1] - t[k]));
+            }
+        }
+    }
+    __shared__ unsigned long long shu[kReduceBlock / 64];
+    const double N = (double)block_sum<unsigned long long>(nused, shu);
+    double mean[kReweightGroup];
+    for (int l = 0; l < kReweightGroup; ++l) {
+        const double S = block_sum<double>(acc[l], shd);
+        mean[l] = N > 0.0 ? S / N : 0.0;
+        acc[l] = 0.0;
+    }
+    if (N > 1.0) {
+        for (uint32_t i = threadIdx.x; i < sg.count; i += kReduceBlock) {
+            const uint32_t o = sg.out_offset + i;
+            if ((a.exNF[o] >> kFlagShift) != 0u) continue;
+            double fac, f;
+            int k;
+            factor_and_pos(o, &fac, &k, &f);
+#pragma unroll
+            for (int l = 0; l < kReweightGroup; ++l) {
+                if ((uint32_t)l < nl) {
+                    const double* t = tab + l * a.n_knots;
+                    const double d = fac * ::exp(t[k] + f * (t[k + 1] - t[k])) - mean[l];
+                    acc[l] += d * d;
+                }
+            }
+        }
+    }
+    for (int l = 0; l < kReweightGroup; ++l) {
+        const double SS = block_sum<double>(acc[l], shd);
+        if (threadIdx.x == 0 && (uint32_t)l < nl) {
+            const size_t ob = (size_t)(l0 + l) * a.total_bins + a.out_base + blockIdx.x;
+            a.flux[ob] = mean[l];
+            a.flux_se[ob] = N > 1.0 ? ::sqrt(SS / (N - 1.0) / N) : 0.0;
+        }
+    }
+}
+
+hipError_t launch_reweight(const ReweightArgs& a, uint32_t n_segs, hipStream_t s)
+{
+    if (n_segs == 0 || a.n_lis == 0) return hipSuccess;
+    const uint32_t groups = (a.n_lis + kReweightGroup - 1) / kReweightGroup;
+    hipLaunchKernelGGL(k_reweight, dim3(n_segs, groups), dim3(kReduceBlock), 0, s, a);
+    return hipGetLastError();
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, uint32_t n)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;

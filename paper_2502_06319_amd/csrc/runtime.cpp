@@ -876,6 +876,56 @@ cosmica_status cosmica_plan_info(const cosmica_plan* p, uint64_t* total_bins,
     return COSMICA_OK;
 }
 
+static_assert(kMaxLisKnots == COSMICA_MAX_LIS_KNOTS, "LDS table size and the ABI limit agree");
+
+cosmica_status cosmica_plan_reweight(cosmica_plan* p, uint32_t n_lis, uint32_t n_knots,
+                                     double lnP0, double dlnP, const double* lnJ, double* flux,
+                                     double* flux_se)
+{
+    if (p == nullptr || lnJ == nullptr || n_lis < 1 || n_lis > COSMICA_MAX_REWEIGHT ||
+        n_knots < 2 || n_knots > (uint32_t)kMaxLisKnots || !std::isfinite(lnP0) ||
+        !finite_pos(dlnP) || !p->executed)
+        return COSMICA_EINVAL;
+    for (size_t i = 0; i < (size_t)n_lis * n_knots; ++i)
+        if (!std::isfinite(lnJ[i])) return COSMICA_EINVAL;
+    cosmica_ctx* ctx = p->ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const uint32_t nb = (uint32_t)p->segs.size();
+    DevSet m(ctx);
+    double* tab = nullptr;
+    double* fd = nullptr;
+    double* sd = nullptr;
+    cosmica_status st;
+    const size_t nout = (size_t)n_lis * nb;
+    if ((st = m.alloc(&tab, (size_t)n_lis * n_knots)) != COSMICA_OK) return st;
+    if ((st = m.alloc(&fd, nout)) != COSMICA_OK) return st;
+    if ((st = m.alloc(&sd, nout)) != COSMICA_OK) return st;
+    HIP_TRY(hipMemcpyAsync(tab, lnJ, (size_t)n_lis * n_knots * 8, hipMemcpyHostToDevice,
+                           ctx->stream));
+    ReweightArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.segs = p->segs_d;
+    a.lis = p->lis_d;
+    a.exP = p->exP;
+    a.exNF = p->exNF;
+    a.exL = p->exL;
+    a.lnJ = tab;
+    a.n_lis = n_lis;
+    a.n_knots = n_knots;
+    a.lnP0 = lnP0;
+    a.dlnP = dlnP;
+    a.seg_base = 0;
+    a.out_base = 0;
+    a.total_bins = nb;
+    a.flux = fd;
+    a.flux_se = sd;
+    HIP_TRY(launch_reweight(a, nb, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (flux) HIP_TRY(hipMemcpy(flux, fd, nout * 8, hipMemcpyDeviceToHost));
+    if (flux_se) HIP_TRY(hipMemcpy(flux_se, sd, nout * 8, hipMemcpyDeviceToHost));
+    return COSMICA_OK;
+}
+
 void cosmica_plan_destroy(cosmica_plan* p)
 {
     if (p == nullptr) return;
