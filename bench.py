@@ -16,7 +16,6 @@ per step) and the FP64 CPU oracle timed on a bounded sample on the host cores.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -29,13 +28,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2502_06319_amd import build as B  # noqa: E402
 from paper_2502_06319_amd import cosmica as C  # noqa: E402
 from paper_2502_06319_amd import scan as S  # noqa: E402
 from paper_2502_06319_amd import workloads as W  # noqa: E402
 
 TUNE_CACHE = os.path.join(ROOT, "paper_2502_06319_amd", "tuned_launch.txt")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "propagate_batched_mixed_traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2502_06319_amd", "csrc", "kernels.hip")
 
 # Algorithmic VALU lane-operations of one Euler-Maruyama step: the gfx950
 # instructions the step's formulas need, one per elementary operation, using
@@ -82,7 +81,8 @@ def tuned_engine_launch(eng: C.Engine, jobs: dict) -> dict:
 
 
 def kernel_digest() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Digest of the device code, the one the launch-shape cache is keyed on."""
+    return B.kernel_id()
 
 
 def read_traffic():
