@@ -47,13 +47,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "propagate_batched_mixed_traffic.t
 # stream, so they are tallied apart and left out of the fraction of peak.
 OPS_PER_STEP = {
     "3d": {"philox4x32_10": 37, "uniforms": 8, "box_muller": 5, "geometry_and_wind": 8,
-           "region_lookup": 5, "beta_kappa": 7, "spiral_weights": 8,
-           "tensor_and_divergence": 8, "drift_prelude": 7, "current_sheet": 48,
+           "region_lookup": 4, "beta_kappa": 7, "spiral_weights": 8,
+           "tensor_and_divergence": 8, "drift_prelude": 7, "current_sheet": 46,
            "gradient_curvature_drift": 12, "sde_drift": 12, "time_step": 12,
-           "tensor_sqrt": 6, "em_update": 20, "reflections": 5, "exit_test": 3},
-    "1d": {"philox4x32_10": 37, "uniforms": 4, "box_muller": 2, "region_lookup": 5,
+           "tensor_sqrt": 6, "em_update": 20, "reflections": 5, "exit_test": 2},
+    "1d": {"philox4x32_10": 37, "uniforms": 4, "box_muller": 2, "region_lookup": 4,
            "beta_kappa": 7, "coefficients": 5, "time_step": 4, "em_update": 13,
-           "exit_test": 3},
+           "exit_test": 2},
 }
 TRANS_PER_STEP = {"3d": 27, "1d": 8}
 # Peak VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T

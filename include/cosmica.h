@@ -37,6 +37,7 @@ extern "C" {
 #define COSMICA_NHIST 129      /* 128 bins of log10(P_ex/P0) over [0,3) + overflow */
 #define COSMICA_MAX_STEP_CAP 16777215u
 #define COSMICA_MAX_ORBIT 1024 /* positions of a moving detection point */
+#define COSMICA_MAX_JOBS 1048576 /* jobs in one plan or cosmica_run call */
 
 typedef enum {
     COSMICA_OK = 0,
@@ -87,7 +88,7 @@ typedef struct {
     double r0_au, theta0_rad, phi0_rad; /* injection point; theta0 in (0, pi) for 3D */
     double b0_nT;            /* > 0 when drift */
     double v_ref_km_s;       /* > 0 when drift */
-    double omega_rad_s;      /* solar rotation, >= 0 */
+    double omega_rad_s;      /* solar rotation, >= 0 (> 0 if any 3D wind speed is 0) */
     double kperp_over_kpar;  /* (0, 1] */
     int32_t polarity;        /* +1 or -1 */
     int32_t drift;           /* 0 or 1 */
@@ -235,7 +236,8 @@ void cosmica_destroy(cosmica_ctx* ctx);
 /* Blocking batch run: all jobs are packed into one flat work queue and
  * integrated by one persistent launch per model (1D / 3D), then reduced per bin
  * (Sec. IV.A: propagation, histogramming, LIS weighting).  results[j] receives
- * job j.  Returns COSMICA_ESTEPCAP (results valid) if any particle hit its cap. */
+ * job j; 1 <= n_jobs <= COSMICA_MAX_JOBS, else COSMICA_EINVAL.  Returns
+ * COSMICA_ESTEPCAP (results valid) if any particle hit its cap. */
 cosmica_status cosmica_run(cosmica_ctx* ctx, const cosmica_job* jobs, int32_t n_jobs,
                            cosmica_precision precision, cosmica_result* results);
 

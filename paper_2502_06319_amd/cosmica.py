@@ -21,6 +21,11 @@ LIB_PATH = os.path.join(HERE, "libcosmica.so")
 
 NHIST = 129
 MAX_REGIONS = 15
+MAX_STEP_CAP = 16777215
+MAX_ORBIT = 1024
+MAX_JOBS = 1048576
+MAX_REWEIGHT = 4096
+MAX_LIS_KNOTS = 256
 MODEL_1D, MODEL_3D = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 PRECISION = {"fp64": PREC_FP64, "mixed": PREC_MIXED, PREC_FP64: PREC_FP64, PREC_MIXED: PREC_MIXED}

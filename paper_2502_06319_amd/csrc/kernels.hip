@@ -89,9 +89,10 @@ struct Mth<float> {
     static __device__ __forceinline__ float atan(float x) { return ::atanf(x); }
     static __device__ __forceinline__ float tanh(float x)
     {
-        // tanh|x| = (1 - e) / (1 + e), e = 2^(-2 |x| log2 e)
-        const float e = __builtin_amdgcn_exp2f(-2.88539008177792681f * fabsf(x));
-        return copysignf((1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e), x);
+        // tanh x = 1 - 2 / (1 + e^(2x)): exact limits +-1 (e^(2x) -> inf or 0),
+        // absolute error ~1e-7 near 0
+        const float e = __builtin_amdgcn_exp2f(2.88539008177792681f * x);
+        return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + e), 1.0f);
     }
     // x - 2 pi floor(x / 2 pi): in [0, 2 pi) up to one rounding
     static __device__ __forceinline__ float fmod2pi(float x)
@@ -200,7 +201,9 @@ struct JobReg {
     double mass;                        // rest energy, used by the energy form
     int32_t energy;
     uint32_t seed_lo, seed_hi, job_tag, step_cap;
-    int32_t nreg, drift, hcs;
+    int32_t nreg, drift;
+    R sheet_off;  // 0 with the current sheet, +inf without it (then Hw = 1)
+    R v_nodrift;  // 0 with drift, 1 without (keeps Gamma finite where V = 0)
 };
 
 template <typename R>
@@ -233,7 +236,9 @@ __device__ __forceinline__ JobReg<R> load_job(const JobDev<R>& J)
     o.step_cap = J.step_cap;
     o.nreg = J.nreg;
     o.drift = J.drift;
-    o.hcs = J.hcs;
+    o.sheet_off = J.hcs ? (R)0 : (R)__builtin_huge_valf();
+    o.v_nodrift = J.drift ? (R)0 : (R)1;
+    if (!J.drift) o.sqA = (R)0;
     return o;
 }
 
@@ -332,16 +337,18 @@ __device__ __forceinline__ void coeffs3d(const JobReg<R>& J, const RegionDev<R>&
     const R rr = r * r;
 
     R vdr = 0, vdt = 0, vdp = 0, Hw = 1;
-    if (J.drift) {
-        const R invV = M::rcp(V);
+    // binary32: computed for every lane, with sqA = 0 and a unit wind speed in
+    // Gamma for jobs without drift (whose wind may be zero), so no branch
+    if (std::is_same<R, float>::value || J.drift) {
+        const R invV = M::rcp(V + J.v_nodrift);
         const R Gam = w * invV;
         const R Gam2 = Gam * Gam;
         // kappa_A / sqrt(1 + Gamma^2) with kappa_A = beta P / (3 |B|)
         const R G = (J.gcoef * bP) * (rr * gq);
         const R Gcot = Gam * cot;
         const R G2cot = Gam * Gcot;
-        R vcr = 0, vct = 0, vcp = 0;
-        if (J.hcs) {
+        R vcr, vct, vcp;
+        {
             // wavy sheet: latitude atan(tan(alpha) sin(phi + Omega r / Vs)),
             // polarity factor tanh((theta_cs - theta) / Delta), Delta = 2 r_L / r
             R sc, cc;
@@ -350,7 +357,8 @@ __device__ __forceinline__ void coeffs3d(const JobReg<R>& J, const RegionDev<R>&
             const R u = lam - M::atan(y);
             // 1/Delta = r |B| / (2 r_L coefficient P), |B| = br0 sqrt(1+Gamma^2) / r^2
             const R invDelta = (J.hb * M::sqrt((R)1.0 + Gam2)) * (invr * M::rcp(P));
-            Hw = M::tanh(u * invDelta);
+            // without the sheet the argument is +inf: Hw = 1, Hp = 0, no sheet drift
+            Hw = M::tanh(u * invDelta + J.sheet_off);
             const R Hp = (R)1.0 - Hw * Hw;
             const R cs = (-g.tana * cc) * M::rcp(y * y + (R)1.0);
             const R gr = cs * g.om_vs;  // d theta_cs / dr
@@ -418,16 +426,30 @@ __device__ __forceinline__ double rigidity_of_T(double T, double M, double abs_z
     return ::sqrt(T * (T + 2.0 * M)) / abs_z;
 }
 
+// A lane's view of its job's region entries: the table's base, the same for
+// every lane, and the byte offset of the job's first entry, so the per-step
+// load is the base plus one 32-bit offset.
+template <typename R>
+struct RegionRef {
+    const RegionDev<R>* base;
+    uint32_t off;
+    __device__ __forceinline__ RegionDev<R> at(int k) const
+    {
+        return *(const RegionDev<R>*)((const char*)base +
+                                      (off + (uint32_t)k * (uint32_t)sizeof(RegionDev<R>)));
+    }
+};
+
 // One EM step of the 3D model.  The caller tests for the exit.
 template <typename R, bool UKEY, bool SHAPED, bool ENERGY>
 __device__ __forceinline__ void step3d(const JobReg<R>& J, const JobDev<R>* __restrict__ jd,
-                                       const RegionDev<R>* __restrict__ reg, PState<R>& s,
+                                       const RegionRef<R> reg, PState<R>& s,
                                        uint32_t pid, uint32_t bin, uint32_t k0, uint32_t k1)
 {
     using M = Mth<R>;
     R z[3];
     normals<R, 3>(UKEY ? k0 : J.seed_lo, UKEY ? k1 : J.seed_hi, s.n, pid, bin, J.job_tag, z);
-    const RegionDev<R> g = reg[region_at<R, SHAPED>(J, jd, s.r, s.th, s.ph)];
+    const RegionDev<R> g = reg.at(region_at<R, SHAPED>(J, jd, s.r, s.th, s.ph));
     const bool efo = ENERGY && J.energy != 0;
     double Pd = s.P;
     if (efo) {
@@ -502,14 +524,14 @@ __device__ __forceinline__ void step3d(const JobReg<R>& J, const JobDev<R>* __re
 
 // One EM step of the radial model: dr = (2k/r - V) ds + sqrt(2k) dW.
 template <typename R, bool UKEY>
-__device__ __forceinline__ void step1d(const JobReg<R>& J, const RegionDev<R>* __restrict__ reg,
+__device__ __forceinline__ void step1d(const JobReg<R>& J, const RegionRef<R> reg,
                                        PState<R>& s, uint32_t pid, uint32_t bin, uint32_t k0,
                                        uint32_t k1)
 {
     using M = Mth<R>;
     R z[1];
     normals<R, 1>(UKEY ? k0 : J.seed_lo, UKEY ? k1 : J.seed_hi, s.n, pid, bin, J.job_tag, z);
-    const RegionDev<R> g = reg[region_of(J, s.r)];
+    const RegionDev<R> g = reg.at(region_of(J, s.r));
     const R r0 = (R)s.r;
     const R r = r0 > M::kRFloor ? r0 : M::kRFloor;
     const R P = (R)s.P;
@@ -555,7 +577,7 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
     PState<R> s = {0.0, 0.0, 0.0, (R)0, (R)0, 0u, 0.0, 0.0};
     uint32_t pid = 0, bin = 0, job = 0, out = 0, seg = 0;
     JobReg<R> J = {};
-    const RegionDev<R>* reg = a.regions;
+    RegionRef<R> reg = {a.regions, 0u};
     const JobDev<R>* jd = a.jobs;  // the lane's job entry (surface constants)
     bool active = false;
     // steps this wave has taken in this launch (wave-uniform), counted against
@@ -606,7 +628,7 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
                     s.lam = J.energy ? q->lam : 0.0;
                 }
                 jd = a.jobs + job;
-                reg = a.regions + (size_t)job * kRegionStride;
+                reg.off = job * (uint32_t)(kRegionStride * sizeof(RegionDev<R>));
                 active = true;
             }
             need = __ballot(!active);
@@ -638,7 +660,7 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
                 out = sg.out_offset + pid;
                 J = load_job(Jd);
                 jd = a.jobs + job;
-                reg = a.regions + (size_t)job * kRegionStride;
+                reg.off = job * (uint32_t)(kRegionStride * sizeof(RegionDev<R>));
                 if (Jd.n_orbit == 0) {
                     s.r = Jd.r0;
                     s.th = (R)Jd.th0;
@@ -694,8 +716,7 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
                     step3d<R, UKEY, SHAPED, ENERGY>(J, jd, reg, s, pid, bin, a.key_lo, a.key_hi);
                 else
                     step1d<R, UKEY>(J, reg, s, pid, bin, a.key_lo, a.key_hi);
-                leave = outside_boundary<R, SHAPED>(J, jd, s.r, s.th, s.ph) || !(s.P == s.P) ||
-                        (ENERGY && !(s.T == s.T)) || s.n >= J.step_cap;
+                leave = outside_boundary<R, SHAPED>(J, jd, s.r, s.th, s.ph) || s.n >= J.step_cap;
             }
             ++wave_steps;
             if (__any(leave) || (sliced && wave_steps >= a.step_budget)) break;

@@ -137,6 +137,12 @@ cosmica_status validate(const cosmica_job* j)
         if (!(h.theta0_rad > 0.0) || !(h.theta0_rad < kPiH)) return COSMICA_EINVAL;
         if (!std::isfinite(h.phi0_rad)) return COSMICA_EINVAL;
         if (!std::isfinite(h.omega_rad_s) || h.omega_rad_s < 0.0) return COSMICA_EINVAL;
+        // the spiral weights V^2 / (V^2 + (Omega r sin theta)^2) need V > 0 or Omega > 0
+        if (h.omega_rad_s == 0.0) {
+            bool calm = !(h.v_fast_km_s > 0.0) || (h.heliosheath == 1 && !(h.v_hs_km_s > 0.0));
+            for (int k = 0; k < h.n_regions; ++k) calm = calm || !(h.v_slow_km_s[k] > 0.0);
+            if (calm) return COSMICA_EINVAL;
+        }
         if (!(h.kperp_over_kpar > 0.0) || !(h.kperp_over_kpar <= 1.0)) return COSMICA_EINVAL;
         if (drift && (!finite_pos(h.b0_nT) || !finite_pos(h.v_ref_km_s))) return COSMICA_EINVAL;
     }
@@ -625,11 +631,17 @@ cosmica_status cosmica_create(cosmica_ctx** out, int device, uint64_t hbm_budget
     return COSMICA_OK;
 }
 
+// the kernels address a job's region entries by a 32-bit byte offset
+static_assert((uint64_t)COSMICA_MAX_JOBS * kRegionStride * sizeof(RegionDev<double>) <= (1ull << 32),
+              "region offsets must fit 32 bits");
+
 cosmica_status cosmica_plan_create(cosmica_ctx* ctx, const cosmica_job* jobs, int32_t n_jobs,
                                    cosmica_precision precision, int32_t want_exits,
                                    cosmica_plan** out)
 {
-    if (ctx == nullptr || out == nullptr || jobs == nullptr || n_jobs < 1) return COSMICA_EINVAL;
+    if (ctx == nullptr || out == nullptr || jobs == nullptr || n_jobs < 1 ||
+        n_jobs > COSMICA_MAX_JOBS)
+        return COSMICA_EINVAL;
     if (precision != COSMICA_PREC_FP64 && precision != COSMICA_PREC_MIXED) return COSMICA_EINVAL;
     *out = nullptr;
     uint64_t total = 0;

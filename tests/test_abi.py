@@ -37,6 +37,14 @@ def test_library_exports_every_declared_function():
     assert set(C.exported_symbols()) == set(names)
 
 
+def test_limits_match_the_header():
+    hdr = open(HEADER).read()
+    for name in ("MAX_REGIONS", "MAX_STEP_CAP", "MAX_ORBIT", "MAX_JOBS", "MAX_REWEIGHT",
+                 "MAX_LIS_KNOTS"):
+        m = re.search(rf"#define COSMICA_{name} (\d+)u?", hdr)
+        assert m and int(m.group(1)) == getattr(C, name), name
+
+
 def test_abi_version_and_strerror():
     lib = C.load()
     assert lib.cosmica_abi_version() == 4
@@ -129,6 +137,12 @@ def test_hcs_requires_drift_and_wind_zero_allowed_without_drift():
     job["helio"]["hcs"] = 0
     job["helio"]["v_slow_km_s"] = [0.0] * 15
     job["helio"]["v_fast_km_s"] = 0.0
+    assert C.validate_job(job) == C.OK
+    # without rotation a zero wind leaves the spiral weights V^2/(V^2 + w^2) undefined
+    job["helio"]["omega_rad_s"] = 0.0
+    assert C.validate_job(job) == C.EINVAL
+    job["helio"]["v_slow_km_s"] = [400.0] * 15
+    job["helio"]["v_fast_km_s"] = 760.0
     assert C.validate_job(job) == C.OK
 
 
