@@ -440,6 +440,15 @@ struct RegionRef {
     }
 };
 
+// phi outside [0, 2 pi) (or NaN).  In binary32 one unsigned compare of the
+// bits: non-negative floats order like their bit patterns, and every negative
+// one (sign bit set) lies above the pattern of 2 pi.
+__device__ __forceinline__ bool outside_turn(float x)
+{
+    return __float_as_uint(x) >= __float_as_uint((float)kTwoPi);
+}
+__device__ __forceinline__ bool outside_turn(double x) { return !(x >= 0.0 && x < kTwoPi); }
+
 // One EM step of the 3D model.  The caller tests for the exit.
 template <typename R, bool UKEY, bool SHAPED, bool ENERGY>
 __device__ __forceinline__ void step3d(const JobReg<R>& J, const JobDev<R>* __restrict__ jd,
@@ -482,14 +491,22 @@ __device__ __forceinline__ void step3d(const JobReg<R>& J, const JobDev<R>* __re
         ph1 = s.ph + c.Ap * dt + (c.Bpr * z[0] + c.Bpp * z[1]) * sdt * (c.invr * c.invst);
         P1 = s.P + c.AP * dt;
     }
-    if (r1 < 0.0) {
-        r1 = -r1;
-        th1 = (R)kPi - th1;
-        ph1 = ph1 + (R)kPi;
+    // reflections through the origin and the poles are rare: a wave branches
+    // to them only when one of its lanes needs them
+    if (__builtin_amdgcn_ballot_w64(r1 < 0.0) != 0) {
+        __asm__ volatile("");  // keeps the block a branch instead of selects
+        if (r1 < 0.0) {
+            r1 = -r1;
+            th1 = (R)kPi - th1;
+            ph1 = ph1 + (R)kPi;
+        }
     }
-    if (th1 < (R)0) {
-        th1 = -th1;
-        ph1 = ph1 + (R)kPi;
+    if (__builtin_amdgcn_ballot_w64(th1 < (R)0) != 0) {
+        __asm__ volatile("");
+        if (th1 < (R)0) {
+            th1 = -th1;
+            ph1 = ph1 + (R)kPi;
+        }
     }
     if (th1 > (R)kPi) {
         th1 = M::fmod2pi(th1);
@@ -498,7 +515,7 @@ __device__ __forceinline__ void step3d(const JobReg<R>& J, const JobDev<R>* __re
             ph1 = ph1 + (R)kPi;
         }
     }
-    if (ph1 < (R)0 || ph1 >= (R)kTwoPi) {
+    if (outside_turn(ph1)) {
         ph1 = M::fmod2pi(ph1);
         if (ph1 < (R)0) ph1 = ph1 + (R)kTwoPi;
     }
