@@ -194,7 +194,11 @@ typedef struct {
     int32_t block;          /* threads per workgroup: 64, 128 or 256 */
     int32_t blocks_per_cu;  /* resident workgroups requested per compute unit (1..32) */
     int32_t chunk;          /* refill chunk: particles handed out per queue grab (>= 1) */
-    int32_t order;          /* 0: bins in submission order; 1: largest bins first */
+    int32_t order;          /* 0: bins in submission order; 1: largest bins first;
+                             * 2: as 1 on a plan's first execution, then (once, after
+                             * waiting for it) most steps per particle first, from the
+                             * counts that execution measured; results never depend
+                             * on the order */
 } cosmica_launch;
 
 /* Timings of the last cosmica_run / cosmica_plan_execute, from HIP events on

@@ -27,10 +27,10 @@ def hipcc() -> str:
 
 
 def kernel_id() -> str:
-    """Digest of the device code (kernels.hip and engine.hpp); the autotuner
-    keys its cache on it."""
+    """Digest of the device code and the runtime that launches it (kernels.hip,
+    engine.hpp, runtime.cpp); the autotuner keys its cache on it."""
     h = hashlib.sha256()
-    for name in ("kernels.hip", "engine.hpp"):
+    for name in ("kernels.hip", "engine.hpp", "runtime.cpp"):
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -379,12 +379,21 @@ struct DevSet {
     }
 };
 
-// Chunks of every segment of a model group, in the requested order.
+// Chunks of every segment of a model group, in the requested order: 0 as
+// given, 1 largest segments first, 2 highest cost per particle first (cost:
+// one value per segment, e.g. the mean steps of an earlier execution; without
+// it, as 1).  Particles are independent and their random numbers do not depend
+// on the schedule, so the order changes only the time to drain the queue:
+// starting the longest paths first keeps them out of the end-of-launch tail.
 void make_chunks(const std::vector<SegmentDev>& segs, const std::vector<uint32_t>& seg_ids,
-                 int chunk, int order, std::vector<ChunkDev>* out)
+                 int chunk, int order, std::vector<ChunkDev>* out,
+                 const std::vector<double>* cost = nullptr)
 {
     std::vector<uint32_t> ids = seg_ids;
-    if (order == 1)
+    if (order == 2 && cost != nullptr)
+        std::stable_sort(ids.begin(), ids.end(),
+                         [&](uint32_t a, uint32_t b) { return (*cost)[a] > (*cost)[b]; });
+    else if (order >= 1)
         std::stable_sort(ids.begin(), ids.end(),
                          [&](uint32_t a, uint32_t b) { return segs[a].count > segs[b].count; });
     const uint32_t c = (uint32_t)std::max(1, chunk);
@@ -419,7 +428,7 @@ bool launch_ok(const cosmica_launch& L)
 {
     return (L.block == 64 || L.block == 128 || L.block == 256) &&
            L.blocks_per_cu >= 0 && L.blocks_per_cu <= 32 && L.chunk >= 1 &&
-           (L.order == 0 || L.order == 1);
+           L.order >= 0 && L.order <= 2;
 }
 
 template <typename R>
@@ -454,6 +463,9 @@ struct cosmica_plan {
     uint64_t total_particles = 0;
     uint64_t model_particles[2] = {0, 0};
     std::vector<ChunkDev> chunks_h[2];
+    std::vector<uint32_t> seg_ids[2];  // segments of each model group
+    int chunk_size[2] = {1, 1};        // refill chunk the queues were cut with
+    bool cost_ordered = false;         // queues re-sorted by measured steps (order 2)
     DevSet mem;
     void* jobs_d = nullptr;
     void* regions_d = nullptr;
@@ -679,6 +691,8 @@ cosmica_status cosmica_plan_create(cosmica_ctx* ctx, const cosmica_job* jobs, in
     for (int m = 0; m < 2; ++m) {
         const cosmica_launch& L = ctx->launch[m][precision];
         make_chunks(p->segs, ids[m], L.chunk, L.order, &p->chunks_h[m]);
+        p->seg_ids[m] = ids[m];
+        p->chunk_size[m] = L.chunk;
     }
     p->key = p->jobs[0].seed;
     p->uniform_key = true;
@@ -723,11 +737,45 @@ cosmica_status cosmica_plan_create(cosmica_ctx* ctx, const cosmica_job* jobs, in
     return COSMICA_OK;
 }
 
+// Queue order 2: after the plan's first execution, re-sort each model group's
+// chunks once by the mean steps per particle that execution measured.  Waits
+// for that execution (the sort needs its counts).
+cosmica_status cost_order(cosmica_plan* p)
+{
+    cosmica_ctx* ctx = p->ctx;
+    bool want = false;
+    for (int m = 0; m < 2; ++m)
+        want |= !p->chunks_h[m].empty() && ctx->launch[m][p->prec].order == 2;
+    if (!want) return COSMICA_OK;
+    const size_t ns = p->segs.size();
+    std::vector<uint64_t> steps(ns);
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipMemcpy(steps.data(), p->steps, ns * 8, hipMemcpyDeviceToHost));
+    std::vector<double> cost(ns);
+    for (size_t i = 0; i < ns; ++i) cost[i] = (double)steps[i] / (double)p->segs[i].count;
+    for (int m = 0; m < 2; ++m) {
+        if (p->chunks_h[m].empty() || ctx->launch[m][p->prec].order != 2) continue;
+        std::vector<ChunkDev> c;
+        make_chunks(p->segs, p->seg_ids[m], p->chunk_size[m], 2, &c, &cost);
+        if (c.size() != p->chunks_h[m].size()) return COSMICA_EDEVICE;
+        p->chunks_h[m].swap(c);
+        HIP_TRY(hipMemcpyAsync(p->chunks_d[m], p->chunks_h[m].data(),
+                               p->chunks_h[m].size() * sizeof(ChunkDev), hipMemcpyHostToDevice,
+                               ctx->stream));
+    }
+    p->cost_ordered = true;
+    return COSMICA_OK;
+}
+
 cosmica_status cosmica_plan_execute(cosmica_plan* p, const cosmica_bins_dev* out)
 {
     if (p == nullptr) return COSMICA_EINVAL;
     cosmica_ctx* ctx = p->ctx;
     HIP_TRY(hipSetDevice(ctx->device));
+    if (p->executed && !p->cost_ordered) {
+        const cosmica_status cs = cost_order(p);
+        if (cs != COSMICA_OK) return cs;
+    }
     HIP_TRY(hipEventRecord(ctx->ev[0], ctx->stream));
     HIP_TRY(launch_fill_u32(p->counters_d, 0u, 8, ctx->stream));
     cosmica_status st = p->prec == COSMICA_PREC_MIXED ? execute_prop<float>(p)
@@ -762,6 +810,10 @@ cosmica_status cosmica_plan_execute(cosmica_plan* p, const cosmica_bins_dev* out
         r.n_nan = out->n_nan;
     }
     HIP_TRY(launch_reduce(r, (uint32_t)p->segs.size(), ctx->stream));
+    // the plan keeps the step counts (queue order 2 sorts by them)
+    if (r.steps != p->steps)
+        HIP_TRY(hipMemcpyAsync(p->steps, r.steps, p->segs.size() * 8, hipMemcpyDeviceToDevice,
+                               ctx->stream));
     HIP_TRY(hipEventRecord(ctx->ev[2], ctx->stream));
     p->executed = true;
     p->own_out = out == nullptr;
@@ -1315,7 +1367,9 @@ cosmica_status sweep(cosmica_ctx* ctx, const cosmica_job* jobs, int n_jobs, int 
     }
     if (st == COSMICA_OK) {
         const cosmica_launch base = best;
-        st = consider(cosmica_launch{base.block, base.blocks_per_cu, base.chunk, 1 - base.order});
+        for (int o = 0; o <= 2 && st == COSMICA_OK; ++o)
+            if (o != base.order)
+                st = consider(cosmica_launch{base.block, base.blocks_per_cu, base.chunk, o});
     }
     if (st != COSMICA_OK) {
         ctx->launch[model][precision] = saved;

@@ -136,6 +136,8 @@ jobs = [W.c2_job(particles_per_bin=500, n_bins=5), W.c1_job(particles_per_bin=20
 jobs[1]["job_tag"] = 9
 stream = torch.cuda.Stream()
 eng = C.Engine(0, stream=stream)               # runs on torch's stream
+for m in (C.MODEL_1D, C.MODEL_3D):             # queue re-sorted after the first execution
+    eng.set_launch(m, "mixed", **dict(eng.get_launch(m, "mixed"), order=2))
 plan = eng.plan(jobs, "mixed")
 plan.execute()
 a = plan.read()
@@ -157,6 +159,17 @@ np.testing.assert_array_equal(out["hist"].cpu().numpy().astype(np.uint32),
 np.testing.assert_array_equal(out["steps"].cpu().numpy().astype(np.uint64),
                               np.concatenate([a[0]["steps"], a[1]["steps"]]))
 plan.destroy()
+# a plan executed only into device buffers sorts by the counts it wrote there
+plan = eng.plan(jobs, "mixed")
+for _ in range(2):
+    for t in out.values():
+        t.zero_()
+    torch.cuda.synchronize()
+    plan.execute(out)
+    stream.synchronize()
+    np.testing.assert_array_equal(out["flux"].cpu().numpy(),
+                                  np.concatenate([a[0]["flux"], a[1]["flux"]]))
+plan.destroy()
 eng.close()
 print("torch-ok")
 """
@@ -176,6 +189,27 @@ def test_torch_stream_and_device_buffers():
                          text=True, timeout=300)
     assert out.returncode == 0, out.stderr[-2000:]
     assert "torch-ok" in out.stdout
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_queue_sorted_by_measured_steps_changes_no_bit(eng, W, precision, restore_launch):
+    """Queue order 2 re-sorts a plan's chunks after its first execution by the
+    steps per particle that execution measured; every execution's results stay
+    bitwise those of the submission order."""
+    jobs = [W.c2_job(particles_per_bin=300, n_bins=6), W.c1_job(particles_per_bin=200),
+            W.c4_jobs(n_sets=1, n_bins=8, n_min=50, n_max=400)[3]]
+    jobs[1]["job_tag"] = 5
+    for m in (C.MODEL_1D, C.MODEL_3D):
+        eng.set_launch(m, precision, **dict(eng.get_launch(m, precision), order=0))
+    ref = eng.run(jobs, precision, exits=True)
+    for m in (C.MODEL_1D, C.MODEL_3D):
+        eng.set_launch(m, precision, **dict(eng.get_launch(m, precision), order=2))
+    plan = eng.plan(jobs, precision, exits=True)
+    for _ in range(3):
+        plan.execute()
+        for a, b in zip(plan.read(exits=True), ref):
+            assert_same(a, b)
+    plan.destroy()
 
 
 def test_timings_count_every_step(eng, W):
