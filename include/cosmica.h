@@ -287,7 +287,8 @@ cosmica_status cosmica_plan_reweight(cosmica_plan* plan, uint32_t n_lis, uint32_
 void cosmica_plan_destroy(cosmica_plan* plan);
 
 /* Launch shape used for (model, precision); the defaults come from the
- * autotuner cache when one was loaded, else built-in values. */
+ * autotuner cache when one was loaded, else built-in values (256 threads, full
+ * residency, 32-particle chunks, order 2). */
 cosmica_status cosmica_set_launch(cosmica_ctx* ctx, cosmica_model model,
                                   cosmica_precision precision, const cosmica_launch* cfg);
 cosmica_status cosmica_get_launch(cosmica_ctx* ctx, cosmica_model model,
@@ -297,7 +298,8 @@ cosmica_status cosmica_get_launch(cosmica_ctx* ctx, cosmica_model model,
  * for (model, precision) (the paper's warps-per-block sweep, Sec. VI "Version 2",
  * generalised).  cache_path, if not NULL, is read first (a hit skips the sweep)
  * and updated afterwards; the cache key includes the device architecture and
- * a digest of the kernel source the library was built from. */
+ * a digest of the kernel and runtime sources the library was built from.  A
+ * candidate replaces the best shape so far only when more than 1% faster. */
 cosmica_status cosmica_tune(cosmica_ctx* ctx, cosmica_model model, cosmica_precision precision,
                             const char* cache_path);
 

@@ -638,7 +638,7 @@ cosmica_status cosmica_create(cosmica_ctx** out, int device, uint64_t hbm_budget
     }
     for (int i = 0; i < 4; ++i) HIP_TRY(hipEventCreate(&ctx->ev[i]));
     for (int m = 0; m < 2; ++m)
-        for (int q = 0; q < 2; ++q) ctx->launch[m][q] = cosmica_launch{256, 0, 256, 0};
+        for (int q = 0; q < 2; ++q) ctx->launch[m][q] = cosmica_launch{256, 0, 32, 2};
     *out = ctx.release();
     return COSMICA_OK;
 }
@@ -1325,14 +1325,18 @@ cosmica_status sweep(cosmica_ctx* ctx, const cosmica_job* jobs, int n_jobs, int 
 {
     const std::string key = tune_key(ctx, model, precision);
     const cosmica_launch saved = ctx->launch[model][precision];
-    cosmica_launch best{256, 0, 256, 0};
+    // Start from full residency, 32-particle chunks and queue order 2 (long
+    // paths kept out of the tail); the other orders are tried last.  Timings
+    // of one shape vary by about 1% from run to run as the device warms, so
+    // another shape replaces the best only when it is more than 1% faster.
+    cosmica_launch best{256, 0, 32, 2};
     double best_rate = -1.0;
     auto consider = [&](const cosmica_launch& c) -> cosmica_status {
         if (!launch_ok(c)) return COSMICA_OK;
         double rate = 0.0;
         cosmica_status st = time_shape(ctx, jobs, n_jobs, model, precision, c, &rate);
         if (st != COSMICA_OK) return st;
-        if (rate > best_rate) {
+        if (best_rate < 0.0 || rate > 1.01 * best_rate) {
             best_rate = rate;
             best = c;
         }
@@ -1360,10 +1364,11 @@ cosmica_status sweep(cosmica_ctx* ctx, const cosmica_job* jobs, int n_jobs, int 
     }
     if (st == COSMICA_OK) {
         const cosmica_launch base = best;
-        for (int ch : {32, 128, 512, 1024})
-            if ((st = consider(cosmica_launch{base.block, base.blocks_per_cu, ch, base.order})) !=
-                COSMICA_OK)
-                break;
+        for (int ch : {32, 128, 512, 1024}) {
+            if (ch == base.chunk) continue;
+            st = consider(cosmica_launch{base.block, base.blocks_per_cu, ch, base.order});
+            if (st != COSMICA_OK) break;
+        }
     }
     if (st == COSMICA_OK) {
         const cosmica_launch base = best;
