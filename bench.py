@@ -192,11 +192,12 @@ def cpu_baseline(seconds_target=15.0):
 
 
 def heliosheath_leg(eng, sync) -> dict:
-    """One pass of the batched workload in a nose-squashed heliosphere with a
-    termination shock and heliosheath (drawn per parameter set), mixed."""
+    """The batched workload in a nose-squashed heliosphere with a termination
+    shock and heliosheath (drawn per parameter set), mixed: one timed pass
+    after one warmup pass (which measures the steps the queue order uses)."""
     hjobs = W.c4_heliosheath_jobs()
     hplan = eng.plan(hjobs, "mixed")
-    hw, hprop, _, hn, _ = time_plan(eng, hplan, 1, 0, sync)
+    hw, hprop, _, hn, _ = time_plan(eng, hplan, 1, 1, sync)
     hplan.destroy()
     ops = sum(OPS_PER_STEP["3d"].values())
     return {"workload": "the batched workload in a nose-squashed heliosphere with a "
@@ -208,11 +209,11 @@ def heliosheath_leg(eng, sync) -> dict:
 
 
 def orbit_leg(eng, sync) -> dict:
-    """One pass of the batched workload seen from a moving detection point: a
-    Ulysses-like polar orbit sampled at 24 equal times, mixed."""
+    """The batched workload seen from a moving detection point: a Ulysses-like
+    polar orbit sampled at 24 equal times, mixed; one timed pass after a warmup."""
     ojobs = W.c4_orbit_jobs()
     oplan = eng.plan(ojobs, "mixed")
-    ow, oprop, _, on, _ = time_plan(eng, oplan, 1, 0, sync)
+    ow, oprop, _, on, _ = time_plan(eng, oplan, 1, 1, sync)
     oplan.destroy()
     ops = sum(OPS_PER_STEP["3d"].values())
     return {"workload": "the batched workload with every bin split over 24 positions of a "
@@ -223,12 +224,12 @@ def orbit_leg(eng, sync) -> dict:
 
 
 def energy_form_leg(eng, sync, momentum_rate) -> dict:
-    """One pass of the batched workload in the energy form of the transport
-    equation (the form of the paper's Versions 0-3), mixed, against the
-    momentum form's rate (Version 6)."""
+    """The batched workload in the energy form of the transport equation (the
+    form of the paper's Versions 0-3), mixed, against the momentum form's rate
+    (Version 6); one timed pass after a warmup, like the momentum form's."""
     ejobs = [dict(j, formulation=1) for j in W.c4_jobs()]
     eplan = eng.plan(ejobs, "mixed")
-    ew, eprop, _, en, _ = time_plan(eng, eplan, 1, 0, sync)
+    ew, eprop, _, en, _ = time_plan(eng, eplan, 1, 1, sync)
     eplan.destroy()
     rate = float(en[0] / ew)
     return {"workload": "the batched workload in the energy form (kinetic energy and the "
@@ -339,7 +340,7 @@ def main():
     plain = None
     if not args.no_plain:
         pplan = eng.plan(pjobs, "fp64")
-        pw, pprop, _, pn, _ = time_plan(eng, pplan, 1, 0, sync)
+        pw, pprop, _, pn, _ = time_plan(eng, pplan, 1, 1, sync)
         pplan.destroy()
         p_rate = pn[0] / (pprop[0] * 1e-3)
         m_rate = steps_per_launch / (prop_avg * 1e-3)
