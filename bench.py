@@ -167,28 +167,36 @@ def serve(eng, seconds, rate, precision, seed=42):
     }
 
 
-def cpu_baseline(seconds_target=15.0):
-    """The FP64 oracle on a bounded, seeded sample of the batched workload."""
+def cpu_baseline(seconds_target=15.0, single_seconds=6.0):
+    """The FP64 oracle on a bounded, seeded sample of the batched workload: on
+    up to 16 host threads (the GPU's host share), and on one core."""
     from oracle import oracle as O
 
     threads = max(1, min(16, os.cpu_count() or 1))
     jobs = W.c4_jobs()
-    rng = np.random.default_rng(7)
-    picks = [(int(rng.integers(len(jobs))), int(rng.integers(30))) for _ in range(4096)]
-    per = 96
-    steps = 0
-    t0 = time.perf_counter()
-    used = 0
-    for ji, b in picks:
-        r = O.run_job(jobs[ji], threads=threads, bins=[b], count=per)[0]
-        steps += int(r["steps"])
-        used += 1
-        if time.perf_counter() - t0 > seconds_target:
-            break
-    wall = time.perf_counter() - t0
-    return {"value": float(steps / wall), "unit": "steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{used} seeded (job, bin) pairs of the batched workload x {per} particles, "
-                      f"{steps} steps in {wall:.1f} s"}
+
+    def timed(n_threads, seconds, seed):
+        # enough particles per call that every thread has several
+        per = 32 * n_threads if n_threads > 1 else 96
+        rng = np.random.default_rng(seed)
+        picks = [(int(rng.integers(len(jobs))), int(rng.integers(30))) for _ in range(4096)]
+        steps = used = 0
+        t0 = time.perf_counter()
+        for ji, b in picks:
+            r = O.run_job(jobs[ji], threads=n_threads, bins=[b], count=per)[0]
+            steps += int(r["steps"])
+            used += 1
+            if time.perf_counter() - t0 > seconds:
+                break
+        wall = time.perf_counter() - t0
+        return steps / wall, (f"{used} seeded (job, bin) pairs of the batched workload x {per} "
+                              f"particles, {steps} steps in {wall:.1f} s")
+
+    rate, sample = timed(threads, seconds_target, 7)
+    rate1, sample1 = timed(1, single_seconds, 8)
+    return {"value": float(rate), "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": sample,
+            "single_core": {"value": float(rate1), "unit": "steps/s", "sample": sample1}}
 
 
 def heliosheath_leg(eng, sync) -> dict:
@@ -258,6 +266,23 @@ def reweight_leg(plan, n_particles, pass_ms) -> dict:
             "propagation_pass_over_reweight": round(pass_ms / ms, 1)}
 
 
+def plain_leg(eng, pjobs, sync, scale, mixed_rate=None) -> dict:
+    """The plain FP64 path (binary64 throughout, software transcendentals) on
+    a particle-count sample of the batched workload: one timed pass after a
+    warmup pass."""
+    ops = sum(OPS_PER_STEP["3d"].values())
+    pplan = eng.plan(pjobs, "fp64")
+    pw, pprop, _, pn, _ = time_plan(eng, pplan, 1, 1, sync)
+    pplan.destroy()
+    p_rate = pn[0] / (pprop[0] * 1e-3)
+    out = {"steps_per_s": float(pn[0] / pw), "propagate_steps_per_s": float(p_rate),
+           "particle_scale": scale, "steps": int(pn[0]), "avg_launch_ms": round(pprop[0], 3),
+           "fp64_ops_frac": round(ops * p_rate / 1e12 / PEAK_TOPS["fp64"], 4)}
+    if mixed_rate is not None:
+        out["mixed_over_plain"] = round(mixed_rate / p_rate, 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,6 +297,8 @@ def main():
     ap.add_argument("--no-orbit", action="store_true")
     ap.add_argument("--no-energy", action="store_true")
     ap.add_argument("--no-reweight", action="store_true")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="only the plain FP64 leg (for profiling its kernel)")
     ap.add_argument("--heliosheath-only", action="store_true",
                     help="time only the heliosheath workload (for profiling)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -280,7 +307,7 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
-    if args.batched_only or args.heliosheath_only:
+    if args.batched_only or args.heliosheath_only or args.plain_only:
         args.no_plain = args.no_serve = args.no_cpu = True
         args.no_heliosheath = args.no_orbit = args.no_energy = args.no_reweight = True
     if args.gpus != 1:
@@ -302,6 +329,12 @@ def main():
         del src, dst
     eng = C.Engine(0)
     jobs = W.c4_jobs()
+    if args.plain_only:
+        pjobs = W.c4_jobs(count_scale=args.plain_scale)
+        log("launch shapes:", tuned_engine_launch(eng, {"fp64": pjobs}))
+        print(json.dumps(plain_leg(eng, pjobs, sync, args.plain_scale)), flush=True)
+        eng.close()
+        return
     pjobs = None if args.no_plain else W.c4_jobs(count_scale=args.plain_scale)
     launch = tuned_engine_launch(eng, {"mixed": jobs} if pjobs is None else
                                  {"mixed": jobs, "fp64": pjobs})
@@ -339,15 +372,8 @@ def main():
 
     plain = None
     if not args.no_plain:
-        pplan = eng.plan(pjobs, "fp64")
-        pw, pprop, _, pn, _ = time_plan(eng, pplan, 1, 1, sync)
-        pplan.destroy()
-        p_rate = pn[0] / (pprop[0] * 1e-3)
-        m_rate = steps_per_launch / (prop_avg * 1e-3)
-        plain = {"steps_per_s": float(pn[0] / pw), "propagate_steps_per_s": float(p_rate),
-                 "particle_scale": args.plain_scale,
-                 "mixed_over_plain": round(m_rate / p_rate, 3),
-                 "fp64_ops_frac": round(ops * p_rate / 1e12 / PEAK_TOPS["fp64"], 4)}
+        plain = plain_leg(eng, pjobs, sync, args.plain_scale,
+                          steps_per_launch / (prop_avg * 1e-3))
         log("plain fp64:", plain)
 
     helio = None
