@@ -198,7 +198,7 @@ struct JobReg {
         adv_frac;
     double rb, inv_shell;
     double rb_tail, ts_nose, ts_tail;  // used by the kernels of squashed heliospheres
-    double mass;                        // rest energy, used by the energy form
+    R mass;                             // rest energy, used by the energy form
     int32_t energy;
     uint32_t seed_lo, seed_hi, job_tag, step_cap;
     int32_t nreg, drift;
@@ -226,7 +226,7 @@ __device__ __forceinline__ JobReg<R> load_job(const JobDev<R>& J)
     o.rb = J.rb;
     o.inv_shell = J.inv_shell;
     o.rb_tail = J.rb_tail;
-    o.mass = J.mass;
+    o.mass = (R)J.mass;
     o.energy = J.energy;
     o.ts_nose = J.ts_nose;
     o.ts_tail = J.ts_tail;
@@ -299,12 +299,11 @@ __device__ __forceinline__ bool outside_boundary(const JobReg<R>& J,
 //   B_phiphi = 2 sqrt(kperp/kpar) kpar / sqrt(2 K_rr), B_thth = sqrt(2 kperp).
 template <typename R, bool FULL>
 __device__ __forceinline__ void coeffs3d(const JobReg<R>& J, const RegionDev<R>& g, double rd,
-                                         double Pd, R th, R ph, Coef3<R>& c)
+                                         R P, R th, R ph, Coef3<R>& c)
 {
     using M = Mth<R>;
     const R r0 = (R)rd;
     const R r = r0 > M::kRFloor ? r0 : M::kRFloor;
-    const R P = (R)Pd;
     R st, ct;
     M::sincos_rad(th, &st, &ct);
     st = st > M::kSinFloor ? st : M::kSinFloor;
@@ -460,18 +459,18 @@ __device__ __forceinline__ void step3d(const JobReg<R>& J, const JobDev<R>* __re
     normals<R, 3>(UKEY ? k0 : J.seed_lo, UKEY ? k1 : J.seed_hi, s.n, pid, bin, J.job_tag, z);
     const RegionDev<R> g = reg.at(region_at<R, SHAPED>(J, jd, s.r, s.th, s.ph));
     const bool efo = ENERGY && J.energy != 0;
-    double Pd = s.P;
+    R Pc = (R)s.P;  // the rigidity the coefficients see
     if (efo) {
         if constexpr (std::is_same<R, float>::value) {
-            // the coefficients see the rigidity of T; binary32 suffices there
-            const float T = (float)s.T, Mr = (float)J.mass;
-            Pd = (double)(M::sqrt(T * (T + 2.0f * Mr)) * M::rcp(J.abs_z));
+            // the rigidity of T; binary32 suffices there
+            const float T = (float)s.T;
+            Pc = M::sqrt(T * (T + 2.0f * J.mass)) * M::rcp(J.abs_z);
         } else {
-            Pd = rigidity_of_T(s.T, J.mass, (double)J.abs_z);
+            Pc = rigidity_of_T(s.T, J.mass, (double)J.abs_z);
         }
     }
     Coef3<R> c;
-    coeffs3d<R, false>(J, g, s.r, Pd, s.th, s.ph, c);
+    coeffs3d<R, false>(J, g, s.r, Pc, s.th, s.ph, c);
     const R dt = c.dt;
     const R sdt = M::sqrt(dt);
     double r1;
@@ -521,12 +520,12 @@ __device__ __forceinline__ void step3d(const JobReg<R>& J, const JobDev<R>* __re
     }
     if (efo) {
         // (1/3) div V, alpha T and the loss at the start of the step
-        const R T = (R)s.T, Mr = (R)J.mass;
+        const R T = (R)s.T, Mr = J.mass;
         const R divV3 = ((R)2.0 / (R)3.0) * c.V * c.invr;
         const R ie = M::rcp(T + Mr);
         const R alphaT = ((T + (R)2.0 * Mr) * ie) * T;
         const R me = Mr * ie;
-        const R L = (R)3.0 * divV3 * ((R)1.0 - ((R)1.0 + me * me) / (R)3.0);
+        const R L = divV3 * ((R)2.0 - me * me);  // (div V) (1 - (1 + me^2) / 3)
         s.T = s.T + (double)(divV3 * alphaT * dt);
         s.lam = s.lam + (double)(L * dt);
         P1 = s.P;  // the rigidity is refreshed from T when the particle leaves
@@ -695,7 +694,7 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
                 if (ENERGY) {
                     // kinetic energy from rigidity: E^2 = (Z P)^2 + M^2
                     const double pc = (double)J.abs_z * sg.P0;
-                    s.T = ::sqrt(pc * pc + J.mass * J.mass) - J.mass;
+                    s.T = ::sqrt(pc * pc + Jd.mass * Jd.mass) - Jd.mass;
                     s.lam = 0.0;
                 }
                 active = true;
@@ -747,7 +746,7 @@ __global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
             else if (!outside)
                 flags = kFlagCapped;
             if (ENERGY && J.energy) {
-                s.P = rigidity_of_T(s.T, J.mass, (double)J.abs_z);
+                s.P = rigidity_of_T(s.T, jd->mass, (double)J.abs_z);
                 a.exL[out] = s.lam;
             }
             a.exP[out] = s.P;
