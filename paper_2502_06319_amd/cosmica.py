@@ -396,7 +396,7 @@ class Engine:
         return Plan(self, h, packs, precision)
 
     # launch shape / tuner / timings
-    def set_launch(self, model, precision, block=256, blocks_per_cu=0, chunk=256, order=0):
+    def set_launch(self, model, precision, block=256, blocks_per_cu=0, chunk=32, order=2):
         c = Launch(block, blocks_per_cu, chunk, order)
         _check(load().cosmica_set_launch(self.handle, model, PRECISION[precision], ctypes.byref(c)),
                "set_launch")

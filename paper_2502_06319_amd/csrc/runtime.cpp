@@ -1006,7 +1006,8 @@ void cosmica_plan_destroy(cosmica_plan* p)
 cosmica_status cosmica_run(cosmica_ctx* ctx, const cosmica_job* jobs, int32_t n_jobs,
                            cosmica_precision precision, cosmica_result* results)
 {
-    if (ctx == nullptr || jobs == nullptr || results == nullptr || n_jobs < 1)
+    if (ctx == nullptr || jobs == nullptr || results == nullptr || n_jobs < 1 ||
+        n_jobs > COSMICA_MAX_JOBS)
         return COSMICA_EINVAL;
     bool want = false;
     for (int j = 0; j < n_jobs; ++j) want |= results[j].exits != nullptr;

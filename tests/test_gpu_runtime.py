@@ -212,6 +212,19 @@ def test_queue_sorted_by_measured_steps_changes_no_bit(eng, W, precision, restor
     plan.destroy()
 
 
+def test_plan_job_count_limit(eng, W):
+    """More than COSMICA_MAX_JOBS jobs (the kernels address region tables by
+    32-bit offsets) is rejected before any job is read."""
+    import ctypes
+
+    pack = C._JobPack(W.c1_job(particles_per_bin=4))
+    jarr = (C.Job * 1)(pack.job)
+    h = ctypes.c_void_p()
+    st = C.load().cosmica_plan_create(eng.handle, jarr, C.MAX_JOBS + 1, C.PREC_MIXED, 0,
+                                      ctypes.byref(h))
+    assert st == C.EINVAL and not h.value
+
+
 def test_timings_count_every_step(eng, W):
     job = W.c2_job(particles_per_bin=400, n_bins=4)
     r = eng.run(job, "mixed")[0]
