@@ -104,6 +104,15 @@ def test_reweight_rejects_bad_calls(eng, W):
     bad[0, 3] = np.nan
     with pytest.raises(C.CosmicaError):
         plan.reweight(lnP0, dlnP, bad)
+    # the limits: spectra per call and knots per table
+    many = np.zeros((C.MAX_REWEIGHT + 1, 2))
+    with pytest.raises(C.CosmicaError):
+        plan.reweight(lnP0, dlnP, many)
+    plan.reweight(lnP0, dlnP, many[:C.MAX_REWEIGHT])
+    with pytest.raises(C.CosmicaError):
+        plan.reweight(lnP0, dlnP, np.zeros((1, C.MAX_LIS_KNOTS + 1)))
+    f, _ = plan.reweight(lnP0, dlnP, np.zeros((1, C.MAX_LIS_KNOTS)))  # J = 1 everywhere
+    assert np.all(f > 0)
     plan.destroy()
 
 
