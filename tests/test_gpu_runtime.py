@@ -225,6 +225,28 @@ def test_plan_job_count_limit(eng, W):
     assert st == C.EINVAL and not h.value
 
 
+def test_rejected_run_leaves_caller_buffers_untouched(eng, W):
+    """cosmica_run validates every job before any device work: on EINVAL the
+    caller's result buffers keep what they held."""
+    import ctypes
+
+    good = W.c1_job(particles_per_bin=16)
+    bad = W.c2_job(particles_per_bin=16, n_bins=4)
+    bad["helio"]["kappa0_cm2_s"] = [-1.0] * 15
+    packs = [C._JobPack(good), C._JobPack(bad)]
+    res = [C._ResultPack(p.n_bins, p.total, True) for p in packs]
+    for r in res:
+        r.flux[:] = 7.0
+        r.hist[:] = 3
+        r.exits["P"] = 5.0
+    jarr = (C.Job * 2)(*[p.job for p in packs])
+    rarr = (C.Result * 2)(*[r.c for r in res])
+    st = C.load().cosmica_run(eng.handle, jarr, 2, C.PREC_MIXED, rarr)
+    assert st == C.EINVAL
+    for r in res:
+        assert np.all(r.flux == 7.0) and np.all(r.hist == 3) and np.all(r.exits["P"] == 5.0)
+
+
 def test_timings_count_every_step(eng, W):
     job = W.c2_job(particles_per_bin=400, n_bins=4)
     r = eng.run(job, "mixed")[0]
