@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import hashlib
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -26,13 +27,22 @@ def hipcc() -> str:
     return h
 
 
+def _code_only(text: str) -> str:
+    """Source without comments and with whitespace collapsed, so that an edit
+    of a comment leaves the digest alone."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return " ".join(text.split())
+
+
 def kernel_id() -> str:
-    """Digest of the device code and the runtime that launches it (kernels.hip,
-    engine.hpp, runtime.cpp); the autotuner keys its cache on it."""
+    """Digest of the code of the device kernels and of the runtime that
+    launches them (kernels.hip, engine.hpp, runtime.cpp; comments excluded);
+    the autotuner keys its cache on it."""
     h = hashlib.sha256()
     for name in ("kernels.hip", "engine.hpp", "runtime.cpp"):
-        with open(os.path.join(CSRC, name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(CSRC, name), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

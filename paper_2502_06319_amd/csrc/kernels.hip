@@ -8,8 +8,13 @@
 //   its idle lanes by ballot rank, so waves stay full until the queue drains.
 //   R = double is the plain FP64 path; R = float is the mixed path (bulk FP32
 //   with the hardware transcendentals, r / t / P accumulated in FP64).
+//   Variants per launch: surface tests (nose-squashed heliosphere with a
+//   heliosheath, Sec. II.B) and the energy form (Eq.(1), with the loss of
+//   Eq.(4)).
 // reduce: one workgroup per rigidity bin; LDS-privatised exit histogram and
-//   fixed-order FP64 sums of the LIS weights (Eq.(4), J = f P^2, L = 0).
+//   fixed-order FP64 sums of the LIS weights (Eq.(4): J = f P^2 with L = 0 in
+//   the momentum form, the loss weight in the energy form).
+// reweight: the same sums for many tabulated spectra over stored exits.
 //
 // No MFMA: the work is per-particle scalar arithmetic, bound by VALU issue
 // and the transcendental unit.
