@@ -256,7 +256,9 @@ cosmica_status cosmica_plan_create(cosmica_ctx* ctx, const cosmica_job* jobs, in
 
 /* Enqueues propagation + reduction on the context's stream and returns without
  * waiting.  out == NULL keeps results in plan-owned device memory (read them
- * with cosmica_plan_read); otherwise results go to the given device buffers. */
+ * with cosmica_plan_read); otherwise results go to the given device buffers.
+ * Under queue order 2 the plan's second execution first waits for the first,
+ * whose per-bin step counts it sorts the queue by (once). */
 cosmica_status cosmica_plan_execute(cosmica_plan* plan, const cosmica_bins_dev* out);
 
 /* Waits for the plan's last execution and copies its plan-owned results into
@@ -277,7 +279,9 @@ cosmica_status cosmica_plan_info(const cosmica_plan* plan, uint64_t* total_bins,
  * be NULL): J_mod(P0) and its standard error for spectrum l, in each job's
  * formulation.  EINVAL if the plan has not been executed, n_lis is outside
  * 1..COSMICA_MAX_REWEIGHT, n_knots outside 2..COSMICA_MAX_LIS_KNOTS, dlnP <= 0
- * or a table value is not finite. */
+ * or a table value is not finite.  Blocking; it holds n_lis * (n_knots + 2 *
+ * total_bins) doubles of device memory for the call (ENOMEM beyond the
+ * context's budget). */
 #define COSMICA_MAX_REWEIGHT 4096
 #define COSMICA_MAX_LIS_KNOTS 256
 cosmica_status cosmica_plan_reweight(cosmica_plan* plan, uint32_t n_lis, uint32_t n_knots,
