@@ -710,3 +710,30 @@ void orc_reweight_bin(const orc_params* p, double P0_gv, const orc_exit* rec, ui
         }
     }
 }
+
+/* The largest exit rigidity, then the counts of ln(P / P0) in n_hist equal
+ * bins up to it (the bin index is floor(n_hist x / x_max), x = ln(P / P0),
+ * clamped to the last bin). */
+void orc_exit_range(double P0_gv, const orc_exit* rec, uint32_t n, uint32_t n_hist, double* p_max,
+                    uint32_t* hist)
+{
+    double pm = 0.0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (rec[i].flags & (ORC_FLAG_CAPPED | ORC_FLAG_NAN)) continue;
+        if (rec[i].P > pm) pm = rec[i].P;
+    }
+    *p_max = pm;
+    for (uint32_t k = 0; k < n_hist; ++k) hist[k] = 0;
+    if (n_hist == 0 || pm == 0.0) return;
+    const double xmax = log(pm / P0_gv);
+    for (uint32_t i = 0; i < n; ++i) {
+        if (rec[i].flags & (ORC_FLAG_CAPPED | ORC_FLAG_NAN)) continue;
+        uint32_t k = 0;
+        if (xmax > 0.0) {
+            const double x = log(rec[i].P / P0_gv);
+            const double f = floor((double)n_hist * x / xmax);
+            k = f <= 0.0 ? 0u : (f >= (double)n_hist ? n_hist - 1 : (uint32_t)f);
+        }
+        hist[k] += 1;
+    }
+}

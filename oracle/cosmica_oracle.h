@@ -187,6 +187,16 @@ void orc_reweight_bin(const orc_params* p, double P0_gv, const orc_exit* rec, ui
                       uint32_t n_lis, uint32_t n_knots, double lnP0, double dlnP,
                       const double* lnJ, double* flux, double* flux_se);
 
+/* Exit histogram over the range the exits reach (Sec. IV.A: the largest exit
+ * energy of the sample sets the histogram's binning).  READING: equal-width
+ * bins in ln(P_ex / P0) over [0, ln(P_max / P0)], P_max the largest exit
+ * rigidity of the bin's used records; the record at P_max falls in the last
+ * bin; with P_max = P0 every record falls in bin 0.  Capped and non-finite
+ * records are left out.  *p_max receives P_max (0 if no record is used);
+ * hist[0..n_hist-1] the counts. */
+void orc_exit_range(double P0_gv, const orc_exit* rec, uint32_t n, uint32_t n_hist, double* p_max,
+                    uint32_t* hist);
+
 #ifdef __cplusplus
 }
 #endif

@@ -144,6 +144,8 @@ def lib():
                                        ctypes.c_uint32, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.orc_lis.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_double]
+        L.orc_exit_range.argtypes = [ctypes.c_double, ctypes.c_void_p, ctypes.c_uint32,
+                                     ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
         L.orc_lis.restype = ctypes.c_double
         _lib = L
     return _lib
@@ -284,6 +286,15 @@ def reweight_bin(p: OrcParams, P0: float, rec: np.ndarray, lnP0: float, dlnP: fl
     lib().orc_reweight_bin(ctypes.byref(p), P0, rec.ctypes.data, len(rec), n_lis, n_knots,
                            lnP0, dlnP, lnJ.ctypes.data, flux.ctypes.data, se.ctypes.data)
     return flux, se
+
+
+def exit_range(P0: float, rec: np.ndarray, n_hist: int):
+    """(P_max, counts of ln(P_ex/P0) in n_hist equal bins over [0, ln(P_max/P0)])."""
+    rec = np.ascontiguousarray(rec, dtype=EXIT_DTYPE)
+    pm = ctypes.c_double()
+    hist = np.zeros(n_hist, dtype=np.uint32)
+    lib().orc_exit_range(P0, rec.ctypes.data, len(rec), n_hist, ctypes.byref(pm), hist.ctypes.data)
+    return pm.value, hist
 
 
 def lis(p: OrcParams, P: float) -> float:
