@@ -359,6 +359,13 @@ def main():
     reweight = None if args.no_reweight else reweight_leg(plan, n_particles, ms_per_step)
     if reweight:
         log("reweight:", reweight)
+        # the paper's binning: largest exit rigidity per bin, 128 bins up to it
+        plan.exit_range(128)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            plan.exit_range(128)
+        reweight["exit_range_128_ms"] = round((time.perf_counter() - t0) / 3 * 1e3, 3)
+        log("exit range:", reweight["exit_range_128_ms"], "ms")
     plan.destroy()
 
     ops = sum(OPS_PER_STEP["3d"].values())

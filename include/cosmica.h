@@ -288,6 +288,21 @@ cosmica_status cosmica_plan_reweight(cosmica_plan* plan, uint32_t n_lis, uint32_
                                      double lnP0, double dlnP, const double* lnJ, double* flux,
                                      double* flux_se);
 
+/* Exit histograms over the range the exits reach, as the paper bins them
+ * (Sec. IV.A: the largest exit energy of the sample sets the binning), from
+ * the plan's last execution: for each bin, p_max = its largest exit rigidity
+ * [GV] (0 if no exit is used) and n_hist counts of ln(P_ex / P0) in equal
+ * bins over [0, ln(p_max / P0)] (the exit at p_max in the last bin; with no
+ * energy change every exit in bin 0).  Capped and non-finite exits are left
+ * out, as in the modulated flux.  p_max: host, total_bins; hist: host,
+ * total_bins * n_hist, bin-major, bins in plan order (either may be NULL).
+ * EINVAL if the plan has not been executed or n_hist is outside
+ * 1..COSMICA_MAX_RANGE_BINS.  Blocking.  The fixed log-ratio histogram of
+ * cosmica_result is the default binning; this one is the paper's. */
+#define COSMICA_MAX_RANGE_BINS 4096
+cosmica_status cosmica_plan_exit_range(cosmica_plan* plan, uint32_t n_hist, double* p_max,
+                                       uint32_t* hist);
+
 void cosmica_plan_destroy(cosmica_plan* plan);
 
 /* Launch shape used for (model, precision); the defaults come from the

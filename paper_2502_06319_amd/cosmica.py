@@ -26,6 +26,7 @@ MAX_ORBIT = 1024
 MAX_JOBS = 1048576
 MAX_REWEIGHT = 4096
 MAX_LIS_KNOTS = 256
+MAX_RANGE_BINS = 4096
 MODEL_1D, MODEL_3D = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 PRECISION = {"fp64": PREC_FP64, "mixed": PREC_MIXED, PREC_FP64: PREC_FP64, PREC_MIXED: PREC_MIXED}
@@ -137,6 +138,8 @@ _SIGS = {
     "cosmica_plan_reweight": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                              ctypes.c_double, ctypes.c_double, c_double_p,
                                              c_double_p, c_double_p]),
+    "cosmica_plan_exit_range": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, c_double_p,
+                                               c_u32_p]),
     "cosmica_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                           ctypes.POINTER(Launch)]),
     "cosmica_get_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
@@ -310,6 +313,18 @@ class Plan:
                                             flux.ctypes.data_as(c_double_p),
                                             se.ctypes.data_as(c_double_p)), "plan_reweight")
         return flux, se
+
+    def exit_range(self, n_hist: int) -> tuple[np.ndarray, np.ndarray]:
+        """Per bin (plan order) the largest exit rigidity of the last execution
+        and the counts of ln(P_ex/P0) in n_hist equal bins up to it:
+        arrays (total_bins,), (total_bins, n_hist)."""
+        nb = self.info()["bins"]
+        pm = np.zeros(nb)
+        hist = np.zeros((nb, n_hist), dtype=np.uint32)
+        _check(load().cosmica_plan_exit_range(self.handle, n_hist,
+                                              pm.ctypes.data_as(c_double_p),
+                                              hist.ctypes.data_as(c_u32_p)), "plan_exit_range")
+        return pm, hist
 
     def destroy(self):
         if self.handle:

@@ -159,6 +159,18 @@ struct ReweightArgs {
     double* flux_se;
 };
 
+// Exit histogram over the reached range: per bin the largest used exit
+// rigidity and the counts of ln(P_ex / P0) in n_hist equal bins up to it.
+constexpr int kMaxRangeBins = 4096;
+struct RangeArgs {
+    const SegmentDev* segs;
+    const double* exP;
+    const uint32_t* exNF;
+    uint32_t n_hist, seg_base, out_base, total_bins;
+    double* p_max;   // total_bins
+    uint32_t* hist;  // total_bins * n_hist
+};
+
 // Launchers (kernels.hip).
 hipError_t launch_propagate_3d_mixed(const PropArgs<float>& a, int grid, int block, hipStream_t s);
 hipError_t launch_propagate_3d_fp64(const PropArgs<double>& a, int grid, int block, hipStream_t s);
@@ -168,6 +180,7 @@ hipError_t occupancy_propagate(int model, int prec, int block, int shaped, int e
                                int* blocks_per_cu);
 hipError_t launch_reduce(const ReduceArgs& a, uint32_t n_segs, hipStream_t s);
 hipError_t launch_reweight(const ReweightArgs& a, uint32_t n_segs, hipStream_t s);
+hipError_t launch_exit_range(const RangeArgs& a, uint32_t n_segs, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint32_t n, hipStream_t s);
 
 // Diagnostics: raw Philox words and normals for counters (i, c1, c2, c3),

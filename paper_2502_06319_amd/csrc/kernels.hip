@@ -1102,6 +1102,74 @@ __global__ void __launch_bounds__(kReduceBlock) k_reweight(const ReweightArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Exit histogram over the reached range (Sec. IV.A: the largest exit energy of
+// the sample sets the histogram's binning): one workgroup per bin takes the
+// largest used exit rigidity P_max, then counts ln(P_ex / P0) in n_hist equal
+// bins over [0, ln(P_max / P0)] (index floor(n_hist x / x_max), the record at
+// P_max in the last bin) with LDS atomics.  Capped and non-finite records are
+// left out.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_max(double v, double* sh)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    const int wid = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+        for (int i = 1; i < kReduceBlock / 64; ++i) t = fmax(t, sh[i]);
+        sh[0] = t;
+    }
+    __syncthreads();
+    const double t = sh[0];
+    __syncthreads();
+    return t;
+}
+
+__global__ void __launch_bounds__(kReduceBlock) k_exit_range(const RangeArgs a)
+{
+    __shared__ uint32_t h[kMaxRangeBins];
+    __shared__ double shd[kReduceBlock / 64];
+    const SegmentDev sg = a.segs[a.seg_base + blockIdx.x];
+    double pm = 0.0;
+    for (uint32_t i = threadIdx.x; i < sg.count; i += kReduceBlock) {
+        const uint32_t o = sg.out_offset + i;
+        if ((a.exNF[o] >> kFlagShift) == 0u) pm = fmax(pm, a.exP[o]);
+    }
+    pm = block_max(pm, shd);
+    for (uint32_t k = threadIdx.x; k < a.n_hist; k += kReduceBlock) h[k] = 0u;
+    __syncthreads();
+    if (pm > 0.0) {
+        const double xmax = ::log(pm / sg.P0);
+        for (uint32_t i = threadIdx.x; i < sg.count; i += kReduceBlock) {
+            const uint32_t o = sg.out_offset + i;
+            if ((a.exNF[o] >> kFlagShift) != 0u) continue;
+            uint32_t k = 0;
+            if (xmax > 0.0) {
+                const double x = ::log(a.exP[o] / sg.P0);
+                const double f = ::floor((double)a.n_hist * x / xmax);
+                k = f <= 0.0 ? 0u : (f >= (double)a.n_hist ? a.n_hist - 1u : (uint32_t)f);
+            }
+            atomicAdd(&h[k], 1u);
+        }
+    }
+    __syncthreads();
+    const size_t ob = (size_t)a.out_base + blockIdx.x;
+    for (uint32_t k = threadIdx.x; k < a.n_hist; k += kReduceBlock)
+        a.hist[ob * a.n_hist + k] = h[k];
+    if (threadIdx.x == 0) a.p_max[ob] = pm;
+}
+
+hipError_t launch_exit_range(const RangeArgs& a, uint32_t n_segs, hipStream_t s)
+{
+    if (n_segs == 0 || a.n_hist == 0 || a.n_hist > (uint32_t)kMaxRangeBins)
+        return n_segs == 0 ? hipSuccess : hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_exit_range, dim3(n_segs), dim3(kReduceBlock), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_reweight(const ReweightArgs& a, uint32_t n_segs, hipStream_t s)
 {
     if (n_segs == 0 || a.n_lis == 0) return hipSuccess;

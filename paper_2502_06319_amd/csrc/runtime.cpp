@@ -990,6 +990,39 @@ cosmica_status cosmica_plan_reweight(cosmica_plan* p, uint32_t n_lis, uint32_t n
     return COSMICA_OK;
 }
 
+cosmica_status cosmica_plan_exit_range(cosmica_plan* p, uint32_t n_hist, double* p_max,
+                                       uint32_t* hist)
+{
+    static_assert(kMaxRangeBins == COSMICA_MAX_RANGE_BINS, "range histogram limit");
+    if (p == nullptr || n_hist < 1 || n_hist > COSMICA_MAX_RANGE_BINS || !p->executed)
+        return COSMICA_EINVAL;
+    cosmica_ctx* ctx = p->ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const uint32_t nb = (uint32_t)p->segs.size();
+    DevSet m(ctx);
+    double* pm = nullptr;
+    uint32_t* h = nullptr;
+    cosmica_status st;
+    if ((st = m.alloc(&pm, nb)) != COSMICA_OK) return st;
+    if ((st = m.alloc(&h, (size_t)nb * n_hist)) != COSMICA_OK) return st;
+    RangeArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.segs = p->segs_d;
+    a.exP = p->exP;
+    a.exNF = p->exNF;
+    a.n_hist = n_hist;
+    a.seg_base = 0;
+    a.out_base = 0;
+    a.total_bins = nb;
+    a.p_max = pm;
+    a.hist = h;
+    HIP_TRY(launch_exit_range(a, nb, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (p_max) HIP_TRY(hipMemcpy(p_max, pm, (size_t)nb * 8, hipMemcpyDeviceToHost));
+    if (hist) HIP_TRY(hipMemcpy(hist, h, (size_t)nb * n_hist * 4, hipMemcpyDeviceToHost));
+    return COSMICA_OK;
+}
+
 void cosmica_plan_destroy(cosmica_plan* p)
 {
     if (p == nullptr) return;

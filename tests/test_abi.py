@@ -40,7 +40,7 @@ def test_library_exports_every_declared_function():
 def test_limits_match_the_header():
     hdr = open(HEADER).read()
     for name in ("MAX_REGIONS", "MAX_STEP_CAP", "MAX_ORBIT", "MAX_JOBS", "MAX_REWEIGHT",
-                 "MAX_LIS_KNOTS"):
+                 "MAX_LIS_KNOTS", "MAX_RANGE_BINS"):
         m = re.search(rf"#define COSMICA_{name} (\d+)u?", hdr)
         assert m and int(m.group(1)) == getattr(C, name), name
 
