@@ -228,7 +228,10 @@ const char* cosmica_strerror(cosmica_status status);
 cosmica_status cosmica_validate_job(const cosmica_job* job);
 
 /* Opens a context on HIP device `device`.  hbm_budget_bytes bounds the device
- * memory the context may hold (0 = 90% of the device's free memory).
+ * memory the context may hold (0 = 90% of the device's free memory).  Device
+ * blocks freed by finished runs and plans stay with the context (up to a
+ * quarter of the budget) for reuse by allocations of the same size, and are
+ * given back first when an allocation would exceed the budget.
  * hip_stream: a hipStream_t to run on, or NULL for a stream the context owns.
  * *out receives the handle (NULL on error). */
 cosmica_status cosmica_create(cosmica_ctx** out, int device, uint64_t hbm_budget_bytes,
@@ -354,7 +357,8 @@ cosmica_status cosmica_wait(cosmica_ctx* ctx, uint64_t ticket, int32_t timeout_m
 /* Cancels a queued or running ticket; its particles are dropped at the next slice. */
 cosmica_status cosmica_cancel(cosmica_ctx* ctx, uint64_t ticket);
 
-/* Serving counters: jobs queued, jobs resident, particles resident, device bytes in use. */
+/* Serving counters: jobs queued, jobs resident, particles resident, device
+ * bytes the context holds (live and kept for reuse). */
 cosmica_status cosmica_serve_stats(cosmica_ctx* ctx, uint64_t* queued, uint64_t* resident,
                                    uint64_t* particles_in_flight, uint64_t* bytes_in_use);
 

@@ -301,7 +301,13 @@ struct cosmica_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     uint64_t budget = 0;
-    std::atomic<uint64_t> in_use{0};
+    std::atomic<uint64_t> in_use{0};  // live and cached device bytes
+    // Freed device blocks kept for reuse by an allocation of the same size
+    // (repeated runs and plans of one shape allocate alike); counted in in_use
+    // and released first when an allocation would exceed the budget.
+    std::mutex cache_mu;
+    std::multimap<size_t, void*> cache;
+    std::atomic<uint64_t> cached{0};
     int num_cus = 0;
     std::string arch;
     cosmica_launch launch[2][2];
@@ -329,11 +335,36 @@ struct cosmica_ctx {
 
 namespace {
 
+// Returns cached blocks to the device until `need` more bytes fit the budget
+// (all of them for need = ~0).
+void cache_trim(cosmica_ctx* ctx, uint64_t need)
+{
+    std::lock_guard<std::mutex> lk(ctx->cache_mu);
+    while (!ctx->cache.empty() && (need == ~0ull || ctx->in_use.load() + need > ctx->budget)) {
+        auto it = std::prev(ctx->cache.end());  // largest first
+        (void)hipFree(it->second);
+        ctx->in_use.fetch_sub(it->first);
+        ctx->cached -= it->first;
+        ctx->cache.erase(it);
+    }
+}
+
 cosmica_status dalloc(cosmica_ctx* ctx, size_t bytes, void** p)
 {
     *p = nullptr;
     if (bytes == 0) return COSMICA_OK;
     bytes = (bytes + 255) & ~(size_t)255;
+    {
+        std::lock_guard<std::mutex> lk(ctx->cache_mu);
+        auto it = ctx->cache.find(bytes);
+        if (it != ctx->cache.end()) {
+            *p = it->second;
+            ctx->cached -= bytes;
+            ctx->cache.erase(it);
+            return COSMICA_OK;
+        }
+    }
+    if (ctx->in_use.load() + bytes > ctx->budget) cache_trim(ctx, bytes);
     const uint64_t cur = ctx->in_use.fetch_add(bytes);
     if (cur + bytes > ctx->budget) {
         ctx->in_use.fetch_sub(bytes);
@@ -348,10 +379,20 @@ cosmica_status dalloc(cosmica_ctx* ctx, size_t bytes, void** p)
     return COSMICA_OK;
 }
 
+// The caller has waited for every use of the block: it is kept for reuse
+// (up to a quarter of the budget in cached blocks), else given back.
 void dfree(cosmica_ctx* ctx, void* p, size_t bytes)
 {
     if (p == nullptr) return;
     bytes = (bytes + 255) & ~(size_t)255;
+    {
+        std::lock_guard<std::mutex> lk(ctx->cache_mu);
+        if (ctx->cached.load() + bytes <= ctx->budget / 4) {
+            ctx->cache.emplace(bytes, p);
+            ctx->cached += bytes;
+            return;
+        }
+    }
     (void)hipFree(p);
     ctx->in_use.fetch_sub(bytes);
 }
@@ -364,6 +405,9 @@ struct DevSet {
     ~DevSet() { release(); }
     void release()
     {
+        // blocks go back to the context's cache: first let every copy or
+        // kernel enqueued on the context's stream finish with them
+        if (!blocks.empty()) (void)hipStreamSynchronize(ctx->stream);
         for (auto& b : blocks) dfree(ctx, b.first, b.second);
         blocks.clear();
     }
@@ -1554,7 +1598,7 @@ uint64_t pool_particles(cosmica_ctx* ctx)
     const char* e = std::getenv("COSMICA_SERVE_POOL");
     long long v = e ? std::strtoll(e, nullptr, 10) : 0;
     uint64_t want = v > 0 ? (uint64_t)v : (256ull << 20);
-    const uint64_t used = ctx->in_use.load();
+    const uint64_t used = ctx->in_use.load() - ctx->cached.load();  // cached blocks give way
     const uint64_t room = ctx->budget > used + (512ull << 20) ? ctx->budget - used - (512ull << 20) : 0;
     return std::min<uint64_t>(want, room / 20);
 }
@@ -2108,6 +2152,7 @@ void cosmica_destroy(cosmica_ctx* ctx)
     if (ctx->serve_stream) (void)hipStreamDestroy(ctx->serve_stream);
     for (int i = 0; i < 4; ++i)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    cache_trim(ctx, ~0ull);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }

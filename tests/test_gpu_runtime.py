@@ -282,3 +282,36 @@ def test_hbm_budget_is_enforced(W):
         assert ex.value.status == C.ENOMEM
         r = e.run(W.c1_job(particles_per_bin=64), "mixed")[0]  # a small job still fits
         assert int(r["hist"].sum()) == 8 * 64
+        # blocks kept for reuse (at most a quarter of the budget: ~7 MB after the
+        # first job here) give way to an allocation that needs the room (~27 MB)
+        small = W.c2_job(particles_per_bin=17500, n_bins=20)
+        big = W.c2_job(particles_per_bin=67500, n_bins=20)
+        for job in (small, big, W.c1_job(particles_per_bin=64)):
+            r = e.run(job, "mixed")[0]
+            assert int(r["hist"].sum()) == int(np.sum(job["particles_per_bin"]))
+        assert e.serve_stats()["bytes_in_use"] <= 32 << 20
+
+
+def test_freed_blocks_are_reused_by_repeated_runs(W):
+    """A repeated run of one shape takes its device blocks from the context's
+    cache: the bytes held stop growing after the first run, and every run's
+    results are bitwise the first's."""
+    jobs = [W.c2_job(particles_per_bin=300, n_bins=5), W.c1_job(particles_per_bin=100)]
+    with C.Engine(0) as e:
+        first = e.run(jobs, "mixed", exits=True)
+        held = e.serve_stats()["bytes_in_use"]
+        assert held > 0
+        for _ in range(4):
+            again = e.run(jobs, "mixed", exits=True)
+            assert e.serve_stats()["bytes_in_use"] == held
+            for a, b in zip(again, first):
+                assert_same(a, b)
+        plan = e.plan(jobs, "fp64")  # other sizes: new blocks, then reuse
+        plan.execute()
+        plan.read()
+        plan.destroy()
+        held64 = e.serve_stats()["bytes_in_use"]
+        plan = e.plan(jobs, "fp64")
+        plan.execute()
+        plan.destroy()
+        assert e.serve_stats()["bytes_in_use"] == held64
