@@ -247,6 +247,26 @@ def test_rejected_run_leaves_caller_buffers_untouched(eng, W):
         assert np.all(r.flux == 7.0) and np.all(r.hist == 3) and np.all(r.exits["P"] == 5.0)
 
 
+def test_non_finite_particles_are_flagged_and_left_out(eng, W):
+    """At 1e20 GV the binary32 square of the rigidity overflows, so the mixed
+    path's coefficients are non-finite at the first step: every particle of
+    that bin leaves flagged non-finite, is counted, and stays out of the
+    histogram and the flux, while the job's other bins are bitwise those of
+    the job without it."""
+    good = W.c2_job(particles_per_bin=200, n_bins=3)
+    bad = dict(good, rigidity_gv=list(good["rigidity_gv"]) + [1e20],
+               particles_per_bin=list(good["particles_per_bin"]) + [50])
+    a = eng.run(good, "mixed", exits=True)[0]
+    b = eng.run(bad, "mixed", exits=True)[0]
+    assert b["n_nan"][3] == 50 and b["n_capped"][3] == 0
+    assert b["flux"][3] == 0.0 and int(b["hist"][3].sum()) == 0
+    ex = b["exits"][-50:]
+    assert np.all(ex["flags"] == 2) and np.all(ex["n"] == 1)
+    for k in KEYS:
+        np.testing.assert_array_equal(b[k][:3], a[k], err_msg=k)
+    np.testing.assert_array_equal(b["exits"][:-50], a["exits"])
+
+
 def test_timings_count_every_step(eng, W):
     job = W.c2_job(particles_per_bin=400, n_bins=4)
     r = eng.run(job, "mixed")[0]
