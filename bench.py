@@ -424,6 +424,13 @@ def main():
         "plain_fp64": plain, "energy_form": energy, "heliosheath": helio, "orbit": orbit,
         "reweight": reweight, "serving": serving,
         "roofline": roofline, "cpu_baseline": cpu,
+        # the paper's speed-ups against its CPU-only code, on its hardware
+        # (abstract; Sec. VII): context, not a target
+        "paper_context": {"first_gpu_port_over_cpu": 40, "last_version_over_cpu": 80,
+                          "hardware": "NVIDIA A30/A40",
+                          "this_over_oracle": (round(float(value) / cpu["value"], 1) if cpu else None),
+                          "this_over_oracle_one_core": (round(float(value) / cpu["single_core"]["value"], 1)
+                                                        if cpu else None)},
     }
     print(json.dumps(line), flush=True)
 
