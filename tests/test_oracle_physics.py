@@ -17,6 +17,8 @@ each compares it with something the mathematics or physics fixes.
   P7  tensor square root, eigen-structure, the Ito divergence terms of K and
       the drift curl, checked by numerical differentiation; field and drift
       coefficient against SI constants; Poisson-kernel exit directions.
+  P28 a step through the origin continues on the antipodal side.
+  P29 the advective step limit moves a particle f_adv r per step.
 """
 import math
 
@@ -401,6 +403,63 @@ def test_p7_exit_directions_follow_poisson_kernel(orc, W, r0, th0):
     cdf = lambda m: (R * R - a * a) / (2 * a) * (1 / np.sqrt(R * R + a * a - 2 * a * R * m)
                                                  - 1 / (R + a))
     assert stats.kstest(mu, cdf).pvalue > 1e-3
+
+
+# --------------------------------------------------------------------------
+# P28: reflection through the origin; P29: the advective step limit
+# --------------------------------------------------------------------------
+def _unit(th, ph):
+    return np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], axis=-1)
+
+
+@pytest.mark.parametrize("th0,ph0", [(math.pi / 4, 0.0), (1.0, 2.0)])
+def test_p28_origin_crossings_land_on_the_antipode(orc, W, th0, ph0):
+    """A step whose radial move passes the Sun carries the particle through the
+    origin, so it continues on the opposite side: the point -|r'| e(th', ph') =
+    |r'| e(pi - th', ph' + pi).  With no spiral (Omega = 0), a field along e_r
+    and kappa_perp = 1e-12 kappa_par the angles stay frozen (noise ~1e-6 rad per
+    step), so every exit lies exactly on the start direction or its antipode,
+    and both occur: with dt = 0.5 r^2 / kappa_par the radial walk is
+    r' = r (2 + z0), through the origin whenever z0 < -2 (2.3 % of steps)."""
+    h = W.helio_3d([1.5e22], [1e-6], [10.0], drift=0, hcs=0, kperp_over_kpar=1e-12,
+                   v_fast=1e-6, r_boundary=1e4, dt_max=1e30, dt_adv_frac=0.0)
+    h["omega_rad_s"] = 0.0
+    h["dt_diff_frac"] = 0.5
+    h["theta0_rad"], h["phi0_rad"] = th0, ph0
+    rec = orc.run_job(W.make_job(h, W.species("p"), [3.0], 4000), threads=8)[0]["records"]
+    assert np.all(rec["flags"] == 0) and np.all(rec["r"] >= 1e4)
+    d = _unit(rec["theta"], rec["phi"]) @ _unit(th0, ph0)
+    assert np.all(np.abs(np.abs(d) - 1.0) < 1e-9), np.sort(np.abs(d))[:5]
+    anti = np.mean(d < 0.0)
+    assert 0.05 < anti < 0.45, anti
+
+
+@pytest.mark.parametrize("P,r,th,phi_part", [(5.0, 10.0, 0.6, True), (20.0, 3.0, 1.45, True),
+                                             (50.0, 40.0, 2.5, False), (2.0, 60.0, 1.2, False)])
+def test_p29_advective_step_moves_f_adv_r(orc, W, P, r, th, phi_part):
+    """With kappa0 = 1e-6 cm^2/s the noise and the diffusive step limit vanish and
+    the drift (wind plus gradient-curvature and sheet drift) sets the step:
+    dt = f_adv r / |A_det|, |A_det| the speed of the drift in the local
+    orthonormal frame.  One Euler-Maruyama step then moves the particle a
+    Cartesian distance f_adv r, up to the frame's curvature (relative O(f_adv)),
+    measured from the positions before and after the step."""
+    f_adv = 1e-7
+    for pol in (1, -1):
+        h = W.helio_3d([1e-6], [400.0], [30.0], polarity=pol, dt_max=1e30, dt_adv_frac=f_adv)
+        job = W.make_job(h, W.species("p"), [P], 1)
+        p = orc.params(job)
+        c = orc.coeffs_3d(p, P, r, th, 0.3)
+        # the drift's theta part (and at two points its phi part) must matter,
+        # or the test could not see their factors r and r sin(theta)
+        comp = np.abs([c["A"][0], r * c["A"][1], r * math.sin(th) * c["A"][2]])
+        assert comp[1] > 0.05 * comp.max()
+        assert comp[2] > 0.1 * comp.max() or not phi_part
+        for i in range(8):
+            st, n, done = orc.advance(p, 0, i, [r, th, 0.3, P, 0.0], 0, 1)
+            assert n == 1 and not done
+            x0 = r * _unit(th, 0.3)
+            x1 = st[0] * _unit(st[1], st[2])
+            assert np.linalg.norm(x1 - x0) == pytest.approx(f_adv * r, rel=1e-6)
 
 
 # --------------------------------------------------------------------------
