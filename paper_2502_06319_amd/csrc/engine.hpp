@@ -54,11 +54,15 @@ struct alignas(16) JobDev {
 
 // One parameter region (a radial shell, or the heliosheath): kappa0 [AU^2/s],
 // slow wind [AU/s], tilt [rad], tan(tilt), omega / slow wind [rad/AU], fast
-// wind [AU/s].
+// wind [AU/s]; om_rev = omega / (2 pi slow wind) [revolutions/AU] in FP64, the
+// current sheet's phase per AU (32 B per entry in binary32, 64 B in binary64).
 template <typename R>
 struct alignas(16) RegionDev {
-    R k0, vs, alpha, tana, om_vs, vf, pad1, pad2;
+    R k0, vs, alpha, tana, om_vs, vf;
+    double om_rev;
 };
+static_assert(sizeof(RegionDev<float>) == 32 && sizeof(RegionDev<double>) == 64,
+              "region entries: two 16-byte loads in binary32");
 
 // One position of a moving detection point.
 struct alignas(16) OrbitDev {

@@ -356,7 +356,16 @@ __device__ __forceinline__ void coeffs3d(const JobReg<R>& J, const RegionDev<R>&
             // wavy sheet: latitude atan(tan(alpha) sin(phi + Omega r / Vs)),
             // polarity factor tanh((theta_cs - theta) / Delta), Delta = 2 r_L / r
             R sc, cc;
-            M::sincos_rad(g.om_vs * r + ph, &sc, &cc);
+            if constexpr (std::is_same<R, float>::value) {
+                // The phase Omega r / Vs reaches hundreds of radians, where a
+                // binary32 ulp is a visible part of the sheet's width: it is
+                // formed from the binary64 r and reduced to one revolution in
+                // binary64, so the sine sees [0, 2) revolutions at any wind speed.
+                const float frac = (float)__builtin_amdgcn_fract(g.om_rev * rd);  // v_fract_f64
+                M::sincos_rev(fmaf(ph, 0.159154943091895336f, frac), &sc, &cc);
+            } else {
+                M::sincos_rad(g.om_vs * r + ph, &sc, &cc);
+            }
             const R y = g.tana * sc;
             const R u = lam - M::atan(y);
             // 1/Delta = r |B| / (2 r_L coefficient P), |B| = br0 sqrt(1+Gamma^2) / r^2

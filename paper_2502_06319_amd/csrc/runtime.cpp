@@ -256,6 +256,14 @@ void make_tables(const JobCopy& jc, JobDev<R>* J, RegionDev<R>* reg, LisDev* lis
     // sheet half-width Delta = 2 r_L / r with r_L = P / (c |B|) [GV, nT -> AU]
     const double rlcoef = 1e18 / (kLightMs * kAuM);
     J->hb = (R)(br0 / (2.0 * rlcoef));
+    if (J->drift == 0) {
+        // the field strength matters only to the drift, and cosmica.h leaves
+        // b0_nT and v_ref_km_s unchecked without it; the binary32 kernel
+        // evaluates the drift terms for every job (times a zero drift sign),
+        // so they must stay finite
+        J->gcoef = (R)0;
+        J->hb = (R)0;
+    }
     J->abs_z = (R)std::fabs((double)s.charge);
     J->mass2 = (R)(s.mass_gev * s.mass_gev);
     J->sqA = (R)((s.charge > 0 ? 1.0 : -1.0) * (double)h.polarity);
@@ -278,6 +286,7 @@ void make_tables(const JobCopy& jc, JobDev<R>* J, RegionDev<R>* reg, LisDev* lis
         g.alpha = (R)alpha;
         g.tana = (R)std::tan(alpha);
         g.om_vs = vs > 0.0 ? (R)(h.omega_rad_s / vs) : (R)0;
+        g.om_rev = vs > 0.0 ? h.omega_rad_s / (2.0 * kPiH * vs) : 0.0;
     }
     lis->norm = s.lis_norm;
     lis->index = s.lis_index;
@@ -1849,8 +1858,15 @@ cosmica_status launch_slice(ServeGroup* g)
     for (const Req* q : g->releasing) a.energy |= q->job.formulation == 1 ? 1u : 0u;
     a.exL = g->exL;
     g->n_chunks_last = nch;
-    HIP_TRY(launch_model<R>(g->model, a, g->grid_var[(a.shaped ? 1 : 0) | (a.energy ? 2 : 0)],
-                            g->block, s));
+    // A wave claims parked particles only until its step budget is spent, so a
+    // slice must hold at least as many lanes as there are parked particles, or
+    // the unclaimed ones would never come back.  The kernel variants for a
+    // squashed heliosphere or the energy form fit fewer waves per CU than the
+    // variant whose slice parked them: such a slice gets the workgroups beyond
+    // residency too; they start as the first ones finish their budget.
+    const int vgrid = g->grid_var[(a.shaped ? 1 : 0) | (a.energy ? 2 : 0)];
+    const int need = (int)(((uint64_t)g->n_resume + (uint64_t)g->block - 1) / (uint64_t)g->block);
+    HIP_TRY(launch_model<R>(g->model, a, std::max(vgrid, need), g->block, s));
     // the host copy of the chunk list must outlive the asynchronous upload
     HIP_TRY(hipStreamSynchronize(s));
     return COSMICA_OK;
@@ -1860,6 +1876,9 @@ cosmica_status collect_slice(ServeGroup* g)
 {
     uint32_t c[4];
     HIP_TRY(hipMemcpy(c, g->counters_d, sizeof(c), hipMemcpyDeviceToHost));
+    // every parked particle of the previous slice was taken up (the slice
+    // launched at least one lane per parked particle)
+    if (c[1] < g->n_resume) return COSMICA_EDEVICE;
     const uint32_t head = std::min(c[0], g->n_chunks_last);
     std::vector<ChunkDev> next(c[3]);
     if (c[3]) HIP_TRY(hipMemcpy(next.data(), g->left_d, c[3] * sizeof(ChunkDev),
