@@ -92,12 +92,18 @@ struct Mth<float> {
         return __builtin_amdgcn_cosf(x * 0.159154943091895336f);
     }
     static __device__ __forceinline__ float atan(float x) { return ::atanf(x); }
-    static __device__ __forceinline__ float tanh(float x)
+    // tanh x and 1 - tanh^2 x, both from e = e^(-2|x|) in [0, 1]:
+    // tanh|x| = (1 - e) / (1 + e) and 1 - tanh^2 x = 4 e / (1 + e)^2.  The second
+    // keeps its relative accuracy where tanh x -> +-1 (1 - tanh^2 would cancel
+    // there: at tanh x = 0.9999997 binary32 leaves it ~20 % off); |x| = inf
+    // gives exactly +-1 and 0.
+    static __device__ __forceinline__ void tanh_sech2(float x, float* t, float* s2)
     {
-        // tanh x = 1 - 2 / (1 + e^(2x)): exact limits +-1 (e^(2x) -> inf or 0),
-        // absolute error ~1e-7 near 0
-        const float e = __builtin_amdgcn_exp2f(2.88539008177792681f * x);
-        return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + e), 1.0f);
+        const float e = __builtin_amdgcn_exp2f(-2.88539008177792681f * fabsf(x));
+        const float q = __builtin_amdgcn_rcpf(1.0f + e);
+        const float eq = e * q;
+        *t = __builtin_copysignf(q - eq, x);
+        *s2 = (4.0f * eq) * q;
     }
     // x - 2 pi floor(x / 2 pi): in [0, 2 pi) up to one rounding
     static __device__ __forceinline__ float fmod2pi(float x)
@@ -119,7 +125,11 @@ struct Mth<double> {
     }
     static __device__ __forceinline__ double cos_rad(double x) { return ::cos(x); }
     static __device__ __forceinline__ double atan(double x) { return ::atan(x); }
-    static __device__ __forceinline__ double tanh(double x) { return ::tanh(x); }
+    static __device__ __forceinline__ void tanh_sech2(double x, double* t, double* s2)
+    {
+        *t = ::tanh(x);
+        *s2 = 1.0 - *t * *t;
+    }
     static __device__ __forceinline__ double fmod2pi(double x) { return ::fmod(x, kTwoPi); }
 };
 
@@ -371,8 +381,8 @@ __device__ __forceinline__ void coeffs3d(const JobReg<R>& J, const RegionDev<R>&
             // 1/Delta = r |B| / (2 r_L coefficient P), |B| = br0 sqrt(1+Gamma^2) / r^2
             const R invDelta = (J.hb * M::sqrt((R)1.0 + Gam2)) * (invr * M::rcp(P));
             // without the sheet the argument is +inf: Hw = 1, Hp = 0, no sheet drift
-            Hw = M::tanh(u * invDelta + J.sheet_off);
-            const R Hp = (R)1.0 - Hw * Hw;
+            R Hp;
+            M::tanh_sech2(u * invDelta + J.sheet_off, &Hw, &Hp);
             const R cs = (-g.tana * cc) * M::rcp(y * y + (R)1.0);
             const R gr = cs * g.om_vs;  // d theta_cs / dr
             const R gph = cs * irs;     // (1/(r sin)) d theta_cs / dphi
@@ -600,8 +610,10 @@ __device__ __forceinline__ uint32_t wave_uniform(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
+// The binary32 energy-form variants are held to 128 VGPRs (4 waves per SIMD).
 template <typename R, bool M3D, bool UKEY, bool SHAPED, bool ENERGY>
-__global__ void __launch_bounds__(256) k_propagate(const PropArgs<R> a)
+__global__ void __launch_bounds__(256, (ENERGY && std::is_same<R, float>::value) ? 4 : 1)
+k_propagate(const PropArgs<R> a)
 {
     const uint32_t lane = __lane_id();
     PState<R> s = {0.0, 0.0, 0.0, (R)0, (R)0, 0u, 0.0, 0.0};

@@ -58,7 +58,7 @@ def test_energy_form_fp64_against_oracle(eng, orc, W, othreads):
     job = _energy_job(W, 400, 8)
     overall, stats = _compare_3d(eng, orc, job, "fp64", othreads, "energy-fp64")
     assert overall >= 0.90
-    for same, dJ, se_pair, r in stats:
+    for same, dJ, se_pair, r, _ in stats:
         assert same >= 0.75
         assert abs(dJ) <= 0.5 * r["flux_se"]
     g = eng.run(job, "fp64", exits=True)[0]
@@ -79,7 +79,7 @@ def test_energy_form_fp64_against_oracle(eng, orc, W, othreads):
 def test_energy_form_mixed_against_oracle(eng, orc, W, othreads):
     job = _energy_job(W, 1000, 8)
     overall, stats = _compare_3d(eng, orc, job, "mixed", othreads, "energy-mixed")
-    for same, dJ, se_pair, r in stats:
+    for same, dJ, se_pair, r, _ in stats:
         N = r["n_used"]
         assert abs(dJ) <= 4.0 * se_pair + 1e-12 * r["flux"]
         assert abs(dJ) <= max(r["flux_se"], r["flux"] / math.sqrt(N))

@@ -64,7 +64,7 @@ def test_polar_orbit_fp64_against_oracle(eng, orc, W, othreads):
     job = W.with_orbit(W.c2_job(particles_per_bin=480, n_bins=8), W.ulysses_like_orbit(24))
     overall, stats = _compare_3d(eng, orc, job, "fp64", othreads, "orbit-fp64")
     assert overall >= 0.90
-    for same, dJ, se_pair, r in stats:
+    for same, dJ, se_pair, r, _ in stats:
         assert same >= 0.75
         assert abs(dJ) <= 0.5 * r["flux_se"]
         assert abs(dJ) <= 4.0 * se_pair + 1e-12 * r["flux"]
@@ -73,7 +73,7 @@ def test_polar_orbit_fp64_against_oracle(eng, orc, W, othreads):
 def test_polar_orbit_mixed_against_oracle(eng, orc, W, othreads):
     job = W.with_orbit(W.c2_job(particles_per_bin=960, n_bins=8), W.ulysses_like_orbit(24))
     overall, stats = _compare_3d(eng, orc, job, "mixed", othreads, "orbit-mixed")
-    for same, dJ, se_pair, r in stats:
+    for same, dJ, se_pair, r, _ in stats:
         N = r["n_used"]
         assert abs(dJ) <= 4.0 * se_pair + 1e-12 * r["flux"]
         assert abs(dJ) <= max(r["flux_se"], r["flux"] / math.sqrt(N))
@@ -92,7 +92,7 @@ def test_orbit_into_the_heliosheath(eng, orc, W, othreads):
     overall, stats = _compare_3d(eng, orc, W.with_orbit(job, orbit), "fp64", othreads,
                                  "orbit-hs-fp64")
     assert overall >= 0.95
-    for same, dJ, se_pair, r in stats:
+    for same, dJ, se_pair, r, _ in stats:
         assert abs(dJ) <= 0.1 * r["flux_se"]
 
 

@@ -119,3 +119,35 @@ def test_serving_rejects_invalid_jobs(W):
         many = W.c2_job(particles_per_bin=10, n_bins=65)  # more bins than a serving slot holds
         with pytest.raises(C.CosmicaError):
             e.submit(many, "mixed")
+
+
+def test_parked_particles_survive_a_smaller_kernel_variant(W, short_slices):
+    """An energy-form request arriving while a large momentum-form request has
+    more particles parked than the energy-form kernel holds lanes (it fits
+    fewer waves per CU) must not strand any of them: both requests complete
+    and equal their stand-alone results bit for bit."""
+    big = W.c2_job(particles_per_bin=20000, n_bins=20)
+    big["helio"]["polarity"] = -1  # sheet-riding paths of 10^4 steps keep every lane busy
+    late = dict(W.c2_job(particles_per_bin=500, n_bins=4), formulation=1, job_tag=7)
+    with C.Engine(0) as e:
+        e.set_launch(1, "mixed", block=256, blocks_per_cu=0)  # full residency: 5 vs 4 waves
+        tb = e.submit(big, "mixed")
+        parked = 0
+        deadline = time.time() + 60.0
+        while time.time() < deadline:
+            st = e.serve_stats()
+            parked = st["particles_in_flight"]
+            done, _ = tb.poll()
+            if parked > 280_000 or done:
+                break
+            time.sleep(0.001)
+        print(f"parked particles when the energy-form request arrived: {parked}", flush=True)
+        assert parked > 262_144  # more than the energy-form variant's lanes
+        tl = e.submit(late, "mixed")
+        assert tl.wait(180000) == C.OK
+        assert tb.wait(180000) == C.OK
+        for j, t in ((big, tb), (late, tl)):
+            alone = e.run(j, "mixed")[0]
+            got = t.result()
+            for k in KEYS:
+                np.testing.assert_array_equal(got[k], alone[k], err_msg=k)
