@@ -8,10 +8,12 @@ persistent propagation kernel, then every bin is histogrammed and LIS-weighted
 by the reduction kernel.  Inputs are resident in device memory (a plan) before
 the timed region starts.
 
-The JSON line also carries: spectra/hour, the plain FP64 GPU path on the same
-workload mix, serving p50/p99 latency under a Poisson request stream, the
-roofline of the propagation kernel (ALU-bound; algorithmic VALU lane-operations
-per step) and the FP64 CPU oracle timed on a bounded sample on the host cores.
+The JSON line also carries: spectra/hour; the first execution of the fresh
+plan; the plain FP64 GPU path on the same workload; serving p50/p99 latency,
+spectra/hour and steps/s under the config-5 Poisson request stream in both
+precisions, and under a stream at twice the batched capacity; the roofline of
+the propagation kernel (ALU-bound; algorithmic VALU lane-operations per step);
+and the FP64 CPU oracle timed on a bounded sample on the host cores.
 """
 from __future__ import annotations
 
@@ -103,10 +105,18 @@ def read_traffic():
         return None
 
 
-def time_plan(eng, plan, steps, warmup, sync):
-    for _ in range(warmup):
+def time_plan(eng, plan, steps, warmup, sync, first=None):
+    """Untimed warmup passes, then `steps` timed passes of one plan.  first, if
+    a dict, receives the plan's first execution (a fresh plan): wall and
+    propagation time and steps."""
+    for k in range(warmup):
+        sync()
+        t0 = time.perf_counter()
         plan.execute()
-        eng.timings()
+        t = eng.timings()
+        if k == 0 and first is not None:
+            first.update(wall_ms=(time.perf_counter() - t0) * 1e3, propagate_ms=t["propagate_ms"],
+                         steps=t["steps"])
     prop, red, nsteps = [], [], []
     sync()
     t0 = time.perf_counter()
@@ -121,8 +131,11 @@ def time_plan(eng, plan, steps, warmup, sync):
     return wall, prop, red, nsteps, t
 
 
-def serve(eng, seconds, rate, precision, seed=42):
-    """Replay a Poisson stream of spectrum requests; latency = arrival -> result."""
+def serve(eng, seconds, rate, precision, seed=42, cut_at=None, poll_s=0.002):
+    """Replay a Poisson stream of spectrum requests (the config-5 request mix);
+    latency = arrival -> result on the host.  cut_at: cancel the requests still
+    waiting for admission at that time (a saturated stream), so the leg ends
+    once the admitted ones finish; they are counted apart."""
     reqs = W.c5_requests(seed=seed, rate_hz=rate, duration_s=seconds)
     tickets = []
     lat = []
@@ -140,39 +153,67 @@ def serve(eng, seconds, rate, precision, seed=42):
     th = threading.Thread(target=submitter)
     th.start()
     steps = 0
-    finished = 0
+    finished = cancelled = 0
     pending = []
-    while not (done.is_set() and finished == len(tickets)):
+    cut = False
+    last_done = t0
+    while not (done.is_set() and finished + cancelled == len(tickets)):
         while len(pending) < len(tickets):
             pending.append(tickets[len(pending)])
+        if cut_at is not None and not cut and time.perf_counter() - t0 >= cut_at:
+            cut = True
+            for arr, tk in pending:
+                if tk is not None and tk.state() == 0:
+                    tk.cancel()  # never admitted: the device did none of its work
         for i, (arr, tk) in enumerate(pending):
             if tk is None:
                 continue
             ok, st = tk.poll()
             if ok:
-                lat.append(time.perf_counter() - t0 - arr)
-                steps += int(tk.result()["steps"].sum())
+                if st == C.ECANCELED:
+                    cancelled += 1
+                else:
+                    lat.append(time.perf_counter() - t0 - arr)
+                    steps += int(tk.result()["steps"].sum())
+                    finished += 1
+                    last_done = time.perf_counter()
                 pending[i] = (arr, None)
-                finished += 1
-        time.sleep(0.002)
+        time.sleep(poll_s)
     th.join()
-    span = time.perf_counter() - t0
+    span = last_done - t0
     lat = np.array(lat)
-    return {
-        "requests": len(reqs), "rate_hz": rate, "seconds": round(span, 2),
-        "p50_latency_s": round(float(np.percentile(lat, 50)), 3) if len(lat) else None,
-        "p99_latency_s": round(float(np.percentile(lat, 99)), 3) if len(lat) else None,
-        "spectra_per_hour": round(len(lat) / span * 3600.0, 1),
+    pct = lambda q: round(float(np.percentile(lat, q)), 3) if len(lat) else None
+    out = {
+        "precision": precision, "rate_hz": rate, "arrival_seconds": seconds,
+        "requests": len(reqs), "completed": finished, "seconds": round(span, 2),
+        "p50_latency_s": pct(50), "p90_latency_s": pct(90), "p99_latency_s": pct(99),
+        "max_latency_s": pct(100),
+        "spectra_per_hour": round(finished / span * 3600.0, 1),
         "steps_per_s": float(steps / span),
     }
+    if cut_at is not None:
+        out["cancelled_unadmitted"] = cancelled
+    return out
+
+
+def host_cores():
+    """(cores the OS reports, cores this process may run on, threads used): a
+    box shares its host among its GPUs, so the oracle uses at most 16 threads,
+    one GPU's share, however many cores the OS shows."""
+    nproc = os.cpu_count() or 1
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = nproc
+    return nproc, allowed, max(1, min(16, allowed))
 
 
 def cpu_baseline(seconds_target=15.0, single_seconds=6.0):
     """The FP64 oracle on a bounded, seeded sample of the batched workload: on
-    up to 16 host threads (the GPU's host share), and on one core."""
+    the host threads of one GPU's share (host_cores), and on one core."""
     from oracle import oracle as O
 
-    threads = max(1, min(16, os.cpu_count() or 1))
+    nproc, allowed, threads = host_cores()
     jobs = W.c4_jobs()
 
     def timed(n_threads, seconds, seed):
@@ -195,14 +236,15 @@ def cpu_baseline(seconds_target=15.0, single_seconds=6.0):
     rate, sample = timed(threads, seconds_target, 7)
     rate1, sample1 = timed(1, single_seconds, 8)
     return {"value": float(rate), "unit": "steps/s", "cores": threads, "kind": "oracle",
-            "sample": sample,
-            "single_core": {"value": float(rate1), "unit": "steps/s", "sample": sample1}}
+            "sample": sample, "host_cores_reported": nproc, "host_cores_allowed": allowed,
+            "single_core": {"value": float(rate1), "unit": "steps/s", "sample": sample1,
+                            "cores": 1}}
 
 
 def heliosheath_leg(eng, sync) -> dict:
     """The batched workload in a nose-squashed heliosphere with a termination
     shock and heliosheath (drawn per parameter set), mixed: one timed pass
-    after one warmup pass (which measures the steps the queue order uses)."""
+    after one warmup pass."""
     hjobs = W.c4_heliosheath_jobs()
     hplan = eng.plan(hjobs, "mixed")
     hw, hprop, _, hn, _ = time_plan(eng, hplan, 1, 1, sync)
@@ -266,20 +308,25 @@ def reweight_leg(plan, n_particles, pass_ms) -> dict:
             "propagation_pass_over_reweight": round(pass_ms / ms, 1)}
 
 
-def plain_leg(eng, pjobs, sync, scale, mixed_rate=None) -> dict:
+def plain_leg(eng, pjobs, sync, scale, mixed=None) -> dict:
     """The plain FP64 path (binary64 throughout, software transcendentals) on
-    a particle-count sample of the batched workload: one timed pass after a
-    warmup pass."""
+    the batched workload (scale 1: the very workload of the headline; below 1 a
+    particle-count sample of it): one timed pass after a warmup pass.
+    mixed: (steps/s, spectra/hour) of the mixed path's timed passes."""
     ops = sum(OPS_PER_STEP["3d"].values())
     pplan = eng.plan(pjobs, "fp64")
     pw, pprop, _, pn, _ = time_plan(eng, pplan, 1, 1, sync)
     pplan.destroy()
     p_rate = pn[0] / (pprop[0] * 1e-3)
     out = {"steps_per_s": float(pn[0] / pw), "propagate_steps_per_s": float(p_rate),
-           "particle_scale": scale, "steps": int(pn[0]), "avg_launch_ms": round(pprop[0], 3),
+           "particle_scale": scale, "particles": W.total_particles(pjobs), "steps": int(pn[0]),
+           "ms_per_pass": round(pw * 1e3, 3), "avg_launch_ms": round(pprop[0], 3),
+           "spectra_per_hour": round(len(pjobs) / pw * 3600.0, 1),
            "fp64_ops_frac": round(ops * p_rate / 1e12 / PEAK_TOPS["fp64"], 4)}
-    if mixed_rate is not None:
-        out["mixed_over_plain"] = round(mixed_rate / p_rate, 3)
+    if mixed is not None:
+        out["mixed_over_plain_steps_per_s"] = round(mixed[0] / (pn[0] / pw), 3)
+        if scale == 1.0:
+            out["mixed_over_plain_spectra_per_hour"] = round(mixed[1] / out["spectra_per_hour"], 3)
     return out
 
 
@@ -288,9 +335,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--plain-scale", type=float, default=0.25,
-                    help="particle-count scale of the plain FP64 comparison pass")
-    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--plain-scale", type=float, default=1.0,
+                    help="particle-count scale of the plain FP64 comparison pass "
+                         "(1: the headline's own workload)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="arrival window of the config-5 stream, each precision")
+    ap.add_argument("--saturate-seconds", type=float, default=60.0,
+                    help="arrival window of the saturated stream (2x capacity)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-heliosheath", action="store_true")
@@ -329,15 +380,19 @@ def main():
         del src, dst
     eng = C.Engine(0)
     jobs = W.c4_jobs()
+    # The FP64 launch shape is tuned on a quarter-size sample of the batched
+    # workload: each of the tuner's ~15 shapes takes two passes, and a full
+    # FP64 pass is ~16 s; the shape it picks is full residency either way.
+    tune_fp64 = W.c4_jobs(count_scale=0.25)
     if args.plain_only:
         pjobs = W.c4_jobs(count_scale=args.plain_scale)
-        log("launch shapes:", tuned_engine_launch(eng, {"fp64": pjobs}))
+        log("launch shapes:", tuned_engine_launch(eng, {"fp64": tune_fp64}))
         print(json.dumps(plain_leg(eng, pjobs, sync, args.plain_scale)), flush=True)
         eng.close()
         return
     pjobs = None if args.no_plain else W.c4_jobs(count_scale=args.plain_scale)
     launch = tuned_engine_launch(eng, {"mixed": jobs} if pjobs is None else
-                                 {"mixed": jobs, "fp64": pjobs})
+                                 {"mixed": jobs, "fp64": tune_fp64})
     log("launch shapes:", launch)
     if args.heliosheath_only:
         print(json.dumps(heliosheath_leg(eng, sync)), flush=True)
@@ -347,13 +402,19 @@ def main():
     n_particles = W.total_particles(jobs)
     plan = eng.plan(jobs, "mixed")
     log(f"batched workload: {len(jobs)} spectra, {n_particles} particles")
-    wall, prop, red, nsteps, last = time_plan(eng, plan, args.steps, args.warmup, sync)
+    first = {}
+    wall, prop, red, nsteps, last = time_plan(eng, plan, args.steps, max(1, args.warmup), sync,
+                                              first)
     steps_total = int(sum(nsteps))
     value = steps_total / wall
     ms_per_step = wall / args.steps * 1e3
     spectra_per_hour = len(jobs) * args.steps / wall * 3600.0
     prop_avg = float(np.mean(prop))
     log(f"mixed: {value:.4e} steps/s, {ms_per_step:.1f} ms per pass, propagate {prop_avg:.1f} ms")
+    first_exec = {"ms": round(first["wall_ms"], 3), "propagate_ms": round(first["propagate_ms"], 3),
+                  "steps_per_s": float(first["steps"] / (first["wall_ms"] * 1e-3)),
+                  "over_timed_passes": round(first["wall_ms"] / ms_per_step, 4)}
+    log("first execution of the fresh plan:", first_exec)
     res = plan.read()
     assert sum(int(r["n_nan"].sum()) for r in res) == 0
     reweight = None if args.no_reweight else reweight_leg(plan, n_particles, ms_per_step)
@@ -379,8 +440,7 @@ def main():
 
     plain = None
     if not args.no_plain:
-        plain = plain_leg(eng, pjobs, sync, args.plain_scale,
-                          steps_per_launch / (prop_avg * 1e-3))
+        plain = plain_leg(eng, pjobs, sync, args.plain_scale, (value, spectra_per_hour))
         log("plain fp64:", plain)
 
     helio = None
@@ -400,8 +460,25 @@ def main():
 
     serving = None
     if not args.no_serve:
-        serving = serve(eng, args.serve_seconds, 5.0, "mixed")
-        log("serving:", serving)
+        # config 5: the same Poisson stream (seed 42, 5 requests/s) in both precisions
+        serving = {"stream": "config 5: Poisson arrivals at 5 requests/s, each one random "
+                             "parameter set and species, 10-50 bins, 1e3-1e5 particles per bin",
+                   "mixed": serve(eng, args.serve_seconds, 5.0, "mixed")}
+        log("serving mixed:", serving["mixed"])
+        serving["fp64"] = serve(eng, args.serve_seconds, 5.0, "fp64")
+        log("serving fp64:", serving["fp64"])
+        m = serving["mixed"]
+        steps_per_req = m["steps_per_s"] * m["seconds"] / max(1, m["completed"])
+        capacity = value / steps_per_req  # requests/s the batched rate would absorb
+        sat = serve(eng, args.saturate_seconds, 2.0 * capacity, "mixed", seed=44,
+                    cut_at=args.saturate_seconds, poll_s=0.02)
+        sat["offered_over_capacity"] = 2.0
+        sat["capacity_req_s"] = round(capacity, 2)
+        sat["frac_of_peak"] = round(sum(OPS_PER_STEP["3d"].values()) * sat["steps_per_s"]
+                                    / 1e12 / PEAK_TOPS["mixed"], 4)
+        sat["served_over_batched"] = round(sat["steps_per_s"] / value, 4)
+        serving["saturated_mixed"] = sat
+        log("serving saturated:", sat)
     eng.close()
 
     cpu = None if args.no_cpu else cpu_baseline()
@@ -421,6 +498,7 @@ def main():
                    "particles": n_particles, "spectra": len(jobs), "seed": 42,
                    "launch": launch["mixed"], "parallelism": "1 GPU"},
         "spectra_per_hour": round(spectra_per_hour, 1),
+        "first_execution": first_exec,
         "plain_fp64": plain, "energy_form": energy, "heliosheath": helio, "orbit": orbit,
         "reweight": reweight, "serving": serving,
         "roofline": roofline, "cpu_baseline": cpu,

@@ -19,8 +19,9 @@
  * allocated by the library, and each has a matching destroy call.
  * Errors: COSMICA_EINVAL is returned before anything is written to outputs;
  * after COSMICA_EDEVICE outputs are undefined.  A context is not thread-safe
- * except for cosmica_poll / cosmica_cancel / cosmica_wait, which may be called
- * from any thread while the serving worker runs.
+ * except for cosmica_poll / cosmica_cancel / cosmica_wait /
+ * cosmica_request_state, which may be called from any thread while the serving
+ * worker runs.
  */
 #ifndef COSMICA_H
 #define COSMICA_H
@@ -195,10 +196,12 @@ typedef struct {
     int32_t blocks_per_cu;  /* resident workgroups requested per compute unit (1..32) */
     int32_t chunk;          /* refill chunk: particles handed out per queue grab (>= 1) */
     int32_t order;          /* 0: bins in submission order; 1: largest bins first;
-                             * 2: as 1 on a plan's first execution, then (once, after
-                             * waiting for it) most steps per particle first, from the
-                             * counts that execution measured; results never depend
-                             * on the order */
+                             * 2: most expected steps per particle first (the
+                             * library's estimate from the drift sign sign(Z) A, the
+                             * shells' mean tilt and the rigidity; ties largest
+                             * first), from the first execution on; serving orders
+                             * each request's own bins so.  Results never depend on
+                             * the order */
 } cosmica_launch;
 
 /* Timings of the last cosmica_run / cosmica_plan_execute, from HIP events on
@@ -259,9 +262,7 @@ cosmica_status cosmica_plan_create(cosmica_ctx* ctx, const cosmica_job* jobs, in
 
 /* Enqueues propagation + reduction on the context's stream and returns without
  * waiting.  out == NULL keeps results in plan-owned device memory (read them
- * with cosmica_plan_read); otherwise results go to the given device buffers.
- * Under queue order 2 the plan's second execution first waits for the first,
- * whose per-bin step counts it sorts the queue by (once). */
+ * with cosmica_plan_read); otherwise results go to the given device buffers. */
 cosmica_status cosmica_plan_execute(cosmica_plan* plan, const cosmica_bins_dev* out);
 
 /* Waits for the plan's last execution and copies its plan-owned results into
@@ -356,6 +357,12 @@ cosmica_status cosmica_wait(cosmica_ctx* ctx, uint64_t ticket, int32_t timeout_m
 
 /* Cancels a queued or running ticket; its particles are dropped at the next slice. */
 cosmica_status cosmica_cancel(cosmica_ctx* ctx, uint64_t ticket);
+
+/* *state = 0 while the ticket waits for admission, 1 while its particles are on
+ * the device, 2 once it is done (finished, failed or cancelled).  For load
+ * shedding: cancelling a ticket in state 0 costs the device nothing.  Returns
+ * COSMICA_ENOTFOUND for an unknown ticket.  Thread-safe like cosmica_poll. */
+cosmica_status cosmica_request_state(cosmica_ctx* ctx, uint64_t ticket, int32_t* state);
 
 /* Serving counters: jobs queued, jobs resident, particles resident, device
  * bytes the context holds (live and kept for reuse). */

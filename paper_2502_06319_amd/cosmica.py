@@ -155,6 +155,8 @@ _SIGS = {
                                     ctypes.POINTER(ctypes.c_int32)]),
     "cosmica_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32]),
     "cosmica_cancel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "cosmica_request_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
+                                             ctypes.POINTER(ctypes.c_int32)]),
     "cosmica_serve_stats": (ctypes.c_int, [ctypes.c_void_p, c_u64_p, c_u64_p, c_u64_p, c_u64_p]),
     "cosmica_probe_rng": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
                                          ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
@@ -355,6 +357,13 @@ class Ticket:
 
     def cancel(self) -> int:
         return load().cosmica_cancel(self.engine.handle, self.id)
+
+    def state(self) -> int:
+        """0 waiting for admission, 1 on the device, 2 done."""
+        s = ctypes.c_int32()
+        _check(load().cosmica_request_state(self.engine.handle, self.id, ctypes.byref(s)),
+               "request_state")
+        return s.value
 
     def result(self) -> dict:
         return self.res.as_dict()

@@ -238,6 +238,7 @@ def test_null_pointers_are_rejected():
     assert lib.cosmica_submit(None, None, 0, None, None) == C.EINVAL
     assert lib.cosmica_poll(None, 1, None) == C.EINVAL
     assert lib.cosmica_cancel(None, 1) == C.EINVAL
+    assert lib.cosmica_request_state(None, 1, None) == C.EINVAL
     assert lib.cosmica_tune(None, 0, 0, None) == C.EINVAL
     lib.cosmica_destroy(None)
     lib.cosmica_plan_destroy(None)

@@ -1,8 +1,8 @@
 """The benchmark's other full-size workloads in the launch shape it times:
 the batched workload in nose-squashed heliospheres with a heliosheath, seen
 from a moving detection point, and in the energy form (4.0e7 particles each).
-For each: invariants over every bin, a second execution (queue re-sorted by
-measured steps, as in the timed passes) bitwise equal to the first, and
+For each: invariants over every bin, a second execution (as in the timed
+passes) bitwise equal to the first, and
 sampled bins against the oracle with the paired statistics of the mixed
 precision tolerance."""
 import math

@@ -270,8 +270,8 @@ def test_full_size_batched_mixed(eng, orc, W, othreads):
     plan = eng.plan(jobs, "mixed", exits=True)
     plan.execute()
     res = plan.read(exits=True)
-    # the benchmark times re-executions, which run with the queue re-sorted by
-    # the measured steps (order 2): bitwise the same results
+    # the benchmark times repeated executions of one plan: bitwise the same
+    # results
     plan.execute()
     again = plan.read(exits=True)
     plan.destroy()

@@ -192,10 +192,10 @@ def test_torch_stream_and_device_buffers():
 
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
-def test_queue_sorted_by_measured_steps_changes_no_bit(eng, W, precision, restore_launch):
-    """Queue order 2 re-sorts a plan's chunks after its first execution by the
-    steps per particle that execution measured; every execution's results stay
-    bitwise those of the submission order."""
+def test_queue_by_expected_steps_changes_no_bit(eng, W, precision, restore_launch):
+    """Queue order 2 starts the bins with the most expected steps per particle
+    first (drift-reversed, wavy-sheet bins ahead of the rest): every
+    execution's results stay bitwise those of the submission order."""
     jobs = [W.c2_job(particles_per_bin=300, n_bins=6), W.c1_job(particles_per_bin=200),
             W.c4_jobs(n_sets=1, n_bins=8, n_min=50, n_max=400)[3]]
     jobs[1]["job_tag"] = 5

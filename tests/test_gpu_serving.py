@@ -151,3 +151,39 @@ def test_parked_particles_survive_a_smaller_kernel_variant(W, short_slices):
             got = t.result()
             for k in KEYS:
                 np.testing.assert_array_equal(got[k], alone[k], err_msg=k)
+
+
+def test_request_state_and_shedding_a_waiting_request(W, short_slices):
+    """cosmica_request_state: 0 while a request waits for admission (here: no
+    room in a 30,000-record pool while a 25,000-particle request is resident),
+    1 while on the device, 2 once done; cancelling a waiting request ends it
+    with ECANCELED and leaves the resident one's result unchanged."""
+    old = os.environ.get("COSMICA_SERVE_POOL")
+    os.environ["COSMICA_SERVE_POOL"] = "30000"
+    try:
+        first = W.c2_job(particles_per_bin=5000, n_bins=5)
+        first["helio"]["polarity"] = -1  # long sheet-riding paths: stays resident a while
+        second = W.c2_job(particles_per_bin=2500, n_bins=4)
+        with C.Engine(0) as e:
+            t1 = e.submit(first, "mixed")
+            t2 = e.submit(second, "mixed")
+            deadline = time.time() + 30.0
+            while t1.state() == 0 and time.time() < deadline:
+                time.sleep(0.001)
+            s1, s2 = t1.state(), t2.state()
+            assert s1 in (1, 2)
+            if s1 == 1:
+                assert s2 == 0  # 25,000 + 10,000 records exceed the pool
+                assert t2.cancel() == C.OK
+                assert t2.wait(60000) == C.ECANCELED
+                assert t2.state() == 2
+            assert t1.wait(120000) == C.OK
+            assert t1.state() == 2
+            np.testing.assert_array_equal(t1.result()["flux"], e.run(first, "mixed")[0]["flux"])
+            s = C.ctypes.c_int32()
+            assert C.load().cosmica_request_state(e.handle, 999999, C.ctypes.byref(s)) == C.ENOTFOUND
+    finally:
+        if old is None:
+            del os.environ["COSMICA_SERVE_POOL"]
+        else:
+            os.environ["COSMICA_SERVE_POOL"] = old
