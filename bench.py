@@ -69,13 +69,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def tuned_engine_launch(eng: C.Engine, jobs: dict) -> dict:
+def tuned_engine_launch(eng: C.Engine, jobs: dict, default=False) -> dict:
     """Launch shapes the tuner picked on the very workloads the bench times
     (jobs: precision -> job list), cached per device architecture, kernel
     digest, model and precision.  A smaller sample gives each lane less work,
     so the end-of-launch tail weighs more and lower occupancy looks better
-    than it is on the real batch."""
+    than it is on the real batch.  default: the library's default shape."""
     out = {}
+    if default:
+        return {prec: eng.get_launch(C.MODEL_3D, prec) for prec in jobs}
     for prec, js in jobs.items():
         log(f"tuning the {prec} launch shape (cache {os.path.basename(TUNE_CACHE)})")
         out[prec] = eng.tune_jobs(js, prec, W.total_particles(js), TUNE_CACHE)
@@ -155,19 +157,29 @@ def serve(eng, seconds, rate, precision, seed=42, cut_at=None, poll_s=0.002):
     steps = 0
     finished = cancelled = 0
     pending = []
+    n_seen = 0
     cut = False
     last_done = t0
     while not (done.is_set() and finished + cancelled == len(tickets)):
-        while len(pending) < len(tickets):
-            pending.append(tickets[len(pending)])
+        while n_seen < len(tickets):
+            pending.append(tickets[n_seen])
+            n_seen += 1
+        if len(pending) > 2048:
+            pending = [x for x in pending if x[1] is not None]
         if cut_at is not None and not cut and time.perf_counter() - t0 >= cut_at:
             cut = True
             for arr, tk in pending:
                 if tk is not None and tk.state() == 0:
                     tk.cancel()  # never admitted: the device did none of its work
+        # admission is first come, first served: only the oldest pending
+        # requests can be done (and, after the cut, the cancelled ones)
+        polled = 0
         for i, (arr, tk) in enumerate(pending):
             if tk is None:
                 continue
+            polled += 1
+            if polled > 512 and not cut:
+                break
             ok, st = tk.poll()
             if ok:
                 if st == C.ECANCELED:
@@ -355,6 +367,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
                     help="time the batched pass only (profiling runs)")
+    ap.add_argument("--default-launch", action="store_true",
+                    help="skip the tuner: the library's default launch shape (quick runs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -392,7 +406,7 @@ def main():
         return
     pjobs = None if args.no_plain else W.c4_jobs(count_scale=args.plain_scale)
     launch = tuned_engine_launch(eng, {"mixed": jobs} if pjobs is None else
-                                 {"mixed": jobs, "fp64": tune_fp64})
+                                 {"mixed": jobs, "fp64": tune_fp64}, args.default_launch)
     log("launch shapes:", launch)
     if args.heliosheath_only:
         print(json.dumps(heliosheath_leg(eng, sync)), flush=True)

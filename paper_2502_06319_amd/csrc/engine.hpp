@@ -118,6 +118,7 @@ struct PropArgs {
     SuspendDev* suspend;
     uint32_t* suspend_count;      // zeroed before launch
     uint32_t step_budget;         // steps per wave per launch (0xffffffff: unlimited)
+    uint64_t slice_ticks;         // launch length in device wall-clock ticks (0: unlimited)
     uint32_t uniform_key;         // 1: every job of the launch has the Philox key below
     uint32_t shaped;              // 1: some job of the launch has a squashed boundary or a heliosheath
     uint32_t energy;              // 1: some job of the launch is in the energy form

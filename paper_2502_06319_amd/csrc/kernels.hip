@@ -612,7 +612,7 @@ __device__ __forceinline__ uint32_t wave_uniform(uint32_t v)
 
 // The binary32 energy-form variants are held to 128 VGPRs (4 waves per SIMD).
 template <typename R, bool M3D, bool UKEY, bool SHAPED, bool ENERGY>
-__global__ void __launch_bounds__(256, (ENERGY && std::is_same<R, float>::value) ? 4 : 1)
+__global__ void __launch_bounds__(256, ((std::is_same<R, float>::value && M3D) ? (ENERGY ? 4 : 1) : 1))
 k_propagate(const PropArgs<R> a)
 {
     const uint32_t lane = __lane_id();
@@ -623,9 +623,13 @@ k_propagate(const PropArgs<R> a)
     const JobDev<R>* jd = a.jobs;  // the lane's job entry (surface constants)
     bool active = false;
     // steps this wave has taken in this launch (wave-uniform), counted against
-    // a.step_budget when the launch is a slice
+    // a.step_budget when the launch is a slice; a slice also ends at a time
+    // every wave reads from the device's constant-rate clock, so the waves stop
+    // together instead of the slice waiting for its slowest wave's budget
     uint32_t wave_steps = 0;
-    const bool sliced = a.step_budget != 0xffffffffu;
+    const bool sliced = a.step_budget != 0xffffffffu || a.slice_ticks != 0;
+    const uint64_t t_stop =
+        a.slice_ticks != 0 ? (uint64_t)wall_clock64() + a.slice_ticks : ~(uint64_t)0;
 
     // wave-uniform refill cursors
     uint32_t c_seg = 0, c_next = 0, c_end = 0;
@@ -748,21 +752,58 @@ k_propagate(const PropArgs<R> a)
         if (!__any(active)) continue;
 
         // Advance the active lanes in lockstep until one of them leaves (boundary
-        // crossing, non-finite state or step cap) or the slice's step budget is
-        // spent.  The loop carries only the particle state, so it stays in place;
-        // why a lane left is worked out afterwards from its state.
-        for (;;) {
-            bool leave = false;
-            if (active) {
-                if (M3D)
-                    step3d<R, UKEY, SHAPED, ENERGY>(J, jd, reg, s, pid, bin, a.key_lo, a.key_hi);
-                else
-                    step1d<R, UKEY>(J, reg, s, pid, bin, a.key_lo, a.key_hi);
-                leave = outside_boundary<R, SHAPED>(J, jd, s.r, s.th, s.ph) || s.n >= J.step_cap;
+        // crossing, non-finite state or step cap) or the slice is over.  The loop
+        // carries only the particle state, so it stays in place; why a lane left
+        // is worked out afterwards from its state.  SK: the Philox key (k0, k1)
+        // is the same for every active lane and sits in scalar registers.
+        // SL: the launch is a serving slice (budget and clock checks).
+        bool slice_over = false;
+        uint32_t k0 = a.key_lo, k1 = a.key_hi;
+        auto lockstep = [&](auto sk, auto sl) {
+            constexpr bool SK = decltype(sk)::value;
+            constexpr bool SL = decltype(sl)::value;
+            for (;;) {
+                bool leave = false;
+                if (active) {
+                    if (M3D)
+                        step3d<R, SK, SHAPED, ENERGY>(J, jd, reg, s, pid, bin, k0, k1);
+                    else
+                        step1d<R, SK>(J, reg, s, pid, bin, k0, k1);
+                    leave = outside_boundary<R, SHAPED>(J, jd, s.r, s.th, s.ph) ||
+                            s.n >= J.step_cap;
+                }
+                ++wave_steps;
+                if constexpr (SL) {
+                    if (wave_steps >= a.step_budget ||
+                        ((wave_steps & 15u) == 0u && (uint64_t)wall_clock64() >= t_stop))
+                        slice_over = true;
+                    if (__any(leave) || slice_over) break;
+                } else {
+                    if (__any(leave)) break;
+                }
             }
-            ++wave_steps;
-            if (__any(leave) || (sliced && wave_steps >= a.step_budget)) break;
-        }
+        };
+        auto keyed = [&](auto sl) {
+            if constexpr (UKEY) {
+                lockstep(std::true_type{}, sl);
+            } else {
+                // Jobs of a launch may carry different seeds, but a wave's lanes
+                // often hold particles of one job (a refill chunk is one bin):
+                // then the key schedule runs on the scalar unit too.
+                const uint64_t act = __ballot(active);
+                const int first = (int)__builtin_ctzll(act);
+                k0 = (uint32_t)__builtin_amdgcn_readlane((int)J.seed_lo, first);
+                k1 = (uint32_t)__builtin_amdgcn_readlane((int)J.seed_hi, first);
+                if (__all(!active || (J.seed_lo == k0 && J.seed_hi == k1)))
+                    lockstep(std::true_type{}, sl);
+                else
+                    lockstep(std::false_type{}, sl);
+            }
+        };
+        if (sliced)
+            keyed(std::true_type{});
+        else
+            keyed(std::false_type{});
         const bool outside = active && outside_boundary<R, SHAPED>(J, jd, s.r, s.th, s.ph);
         const bool bad_T = ENERGY && !(s.T == s.T);
         if (active && (outside || !(s.P == s.P) || bad_T || s.n >= J.step_cap)) {
@@ -786,7 +827,7 @@ k_propagate(const PropArgs<R> a)
             if (a.job_done != nullptr) atomicAdd(&a.job_done[job], 1u);
             active = false;
         }
-        if (sliced && wave_steps >= a.step_budget) {
+        if (slice_over) {
             // slice over: park the wave's particles for the next launch and stop
             // taking work
             if (active) {

@@ -318,6 +318,7 @@ struct cosmica_ctx {
     std::multimap<size_t, void*> cache;
     std::atomic<uint64_t> cached{0};
     int num_cus = 0;
+    int wall_khz = 0;  // rate of the device's constant-rate clock [kHz]
     std::string arch;
     cosmica_launch launch[2][2];
     cosmica_timings timings{};
@@ -703,6 +704,12 @@ cosmica_status cosmica_create(cosmica_ctx** out, int device, uint64_t hbm_budget
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, device));
     ctx->num_cus = prop.multiProcessorCount;
+    if (hipDeviceGetAttribute(&ctx->wall_khz, hipDeviceAttributeWallClockRate, device) !=
+            hipSuccess ||
+        ctx->wall_khz <= 0) {
+        (void)hipGetLastError();
+        ctx->wall_khz = 0;  // slices then end by their step budget only
+    }
     ctx->arch = prop.gcnArchName;
     size_t freeb = 0, totalb = 0;
     HIP_TRY(hipMemGetInfo(&freeb, &totalb));
@@ -1532,6 +1539,7 @@ struct Req {
     bool cancel_sent = false;
     int slot = -1;
     uint64_t ex0 = 0;
+    uint64_t ring_end = 0;  // queue position just past the request's last chunk
 };
 
 struct ServeGroup {
@@ -1547,9 +1555,14 @@ struct ServeGroup {
     uint32_t* cancel_d = nullptr;
     uint32_t* done_d = nullptr;
     SegmentDev* segs_d = nullptr;
-    ChunkDev* chunks_d = nullptr;
-    uint32_t chunks_cap = 0;
-    void* chunks_block = nullptr;
+    // Work queue of the admitted requests' chunks, resident on the device:
+    // entries [q_head, q_tail) of ring_d are still to be issued.  A request's
+    // chunks are uploaded once, when it is admitted; a slice issues from q_head
+    // on, and chunks a wave held unfinished when the slice ended go back in
+    // front of q_head.
+    ChunkDev* ring_d = nullptr;
+    uint64_t ring_cap = 0;
+    uint64_t q_head = 0, q_tail = 0;
     uint64_t pool_cap = 0;
     double* exL = nullptr;  // energy form: allocated when the first energy-form request arrives
     double* exP = nullptr;
@@ -1572,9 +1585,9 @@ struct ServeGroup {
     std::vector<int> free_slots;
     std::vector<SegmentDev> segs_h;
     std::map<uint64_t, uint64_t> free_ranges;  // offset -> length of free pool ranges
-    std::vector<ChunkDev> carry;               // chunks to hand to the next slice
+    std::vector<uint8_t> slot_cancelled;       // per slot: its request was cancelled
     std::vector<Req*> resident;
-    std::vector<Req*> releasing;               // cancelled, freed after the next slice
+    std::vector<Req*> releasing;               // cancelled, freed once none of their work is queued
     int grid = 0, block = 256;
     int grid_var[4] = {0, 0, 0, 0};  // by (shaped | 2 energy)
     uint32_t n_chunks_last = 0;
@@ -1585,11 +1598,23 @@ cosmica_ctx::~cosmica_ctx() = default;
 
 namespace {
 
+// A serving slice ends after COSMICA_SLICE_MS milliseconds (default 6; the
+// device's constant-rate clock, read by every wave) or, if set, after
+// COSMICA_SLICE_STEPS steps of each wave, whichever comes first.
 uint32_t slice_steps()
 {
     const char* e = std::getenv("COSMICA_SLICE_STEPS");
     long v = e ? std::strtol(e, nullptr, 10) : 0;
-    return v > 0 ? (uint32_t)v : 2048u;
+    return v > 0 ? (uint32_t)std::min<long>(v, 0xfffffffel) : 0xffffffffu;
+}
+
+uint64_t slice_ticks(const cosmica_ctx* ctx)
+{
+    const char* e = std::getenv("COSMICA_SLICE_MS");
+    double ms = e ? std::strtod(e, nullptr) : 0.0;
+    if (!(ms > 0.0)) ms = 6.0;
+    if (ctx->wall_khz <= 0) return 0;
+    return std::max<uint64_t>(1, (uint64_t)(ms * (double)ctx->wall_khz));
 }
 
 uint64_t pool_particles(cosmica_ctx* ctx)
@@ -1656,6 +1681,10 @@ cosmica_status group_create(cosmica_ctx* ctx, int model, int prec, ServeGroup** 
     if ((st = g->mem.alloc(&g->exP, g->pool_cap)) != COSMICA_OK) return st;
     if ((st = g->mem.alloc(&g->exT, g->pool_cap)) != COSMICA_OK) return st;
     if ((st = g->mem.alloc(&g->exNF, g->pool_cap)) != COSMICA_OK) return st;
+    g->ring_cap = 1u << 20;
+    if ((st = dalloc(ctx, g->ring_cap * sizeof(ChunkDev), (void**)&g->ring_d)) != COSMICA_OK)
+        return st;
+    g->slot_cancelled.assign(S, 0);
     g->free_ranges[0] = g->pool_cap;
     for (int s = (int)S - 1; s >= 0; --s) g->free_slots.push_back(s);
     g->segs_h.resize((size_t)S * B);
@@ -1694,6 +1723,53 @@ void pool_give(ServeGroup* g, uint64_t off, uint64_t n)
             g->free_ranges.erase(it);
         }
     }
+}
+
+// Appends chunks at the queue's tail.  When the buffer's end is reached the
+// queued entries move to its start (or to a buffer twice as large).
+cosmica_status ring_append(ServeGroup* g, const std::vector<ChunkDev>& ch)
+{
+    cosmica_ctx* ctx = g->ctx;
+    hipStream_t s = ctx->serve_stream;
+    const uint64_t n = ch.size(), live = g->q_tail - g->q_head;
+    if (g->q_tail + n > g->ring_cap) {
+        uint64_t cap = g->ring_cap;
+        while (live + n > cap / 2) cap *= 2;  // room to spare after the move
+        ChunkDev* dst = g->ring_d;
+        if (cap != g->ring_cap) {
+            cosmica_status st = dalloc(ctx, cap * sizeof(ChunkDev), (void**)&dst);
+            if (st != COSMICA_OK) return st;
+        }
+        if (live > 0) {
+            if (dst != g->ring_d || live <= g->q_head) {
+                // source and destination do not overlap
+                HIP_TRY(hipMemcpyAsync(dst, g->ring_d + g->q_head, live * sizeof(ChunkDev),
+                                       hipMemcpyDeviceToDevice, s));
+            } else {
+                std::vector<ChunkDev> tmp(live);
+                HIP_TRY(hipMemcpyAsync(tmp.data(), g->ring_d + g->q_head, live * sizeof(ChunkDev),
+                                       hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                HIP_TRY(hipMemcpyAsync(dst, tmp.data(), live * sizeof(ChunkDev),
+                                       hipMemcpyHostToDevice, s));
+            }
+        }
+        HIP_TRY(hipStreamSynchronize(s));
+        if (dst != g->ring_d) {
+            dfree(ctx, g->ring_d, g->ring_cap * sizeof(ChunkDev));
+            g->ring_d = dst;
+            g->ring_cap = cap;
+        }
+        g->q_head = 0;
+        g->q_tail = live;
+    }
+    if (n > 0)
+        HIP_TRY(hipMemcpyAsync(g->ring_d + g->q_tail, ch.data(), n * sizeof(ChunkDev),
+                               hipMemcpyHostToDevice, s));
+    g->q_tail += n;
+    // pageable source: the copy must be complete before the vector goes
+    HIP_TRY(hipStreamSynchronize(s));
+    return COSMICA_OK;
 }
 
 template <typename R>
@@ -1789,9 +1865,13 @@ cosmica_status admit(cosmica_ctx* ctx)
         std::vector<double> cost(g->segs_h.size(), 0.0);
         for (size_t b = 0; b < q->job.rig.size(); ++b)
             cost[s0 + b] = expected_steps(q->job, q->job.rig[b]);
-        make_chunks(g->segs_h, ids, L.chunk, L.order, &g->carry, &cost);
+        std::vector<ChunkDev> chunks;
+        make_chunks(g->segs_h, ids, L.chunk, L.order, &chunks, &cost);
         cosmica_status st = q->prec == 1 ? upload_slot<float>(g, q) : upload_slot<double>(g, q);
         if (st != COSMICA_OK) return st;
+        g->slot_cancelled[q->slot] = 0;
+        if ((st = ring_append(g, chunks)) != COSMICA_OK) return st;
+        q->ring_end = g->q_tail;
         uint32_t zero = 0;
         HIP_TRY(hipMemcpy(g->done_d + q->slot, &zero, 4, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(g->cancel_d + q->slot, &zero, 4, hipMemcpyHostToDevice));
@@ -1806,24 +1886,7 @@ cosmica_status launch_slice(ServeGroup* g)
 {
     cosmica_ctx* ctx = g->ctx;
     hipStream_t s = ctx->serve_stream;
-    const uint32_t nch = (uint32_t)g->carry.size();
-    if (nch > g->chunks_cap) {
-        if (g->chunks_block) {
-            dfree(ctx, g->chunks_block, (size_t)g->chunks_cap * sizeof(ChunkDev));
-            g->chunks_block = nullptr;
-            g->chunks_d = nullptr;
-        }
-        const uint32_t cap = std::max<uint32_t>(nch * 2, 4096);
-        void* p = nullptr;
-        cosmica_status st = dalloc(ctx, (size_t)cap * sizeof(ChunkDev), &p);
-        if (st != COSMICA_OK) return st;
-        g->chunks_block = p;
-        g->chunks_d = (ChunkDev*)p;
-        g->chunks_cap = cap;
-    }
-    if (nch)
-        HIP_TRY(hipMemcpyAsync(g->chunks_d, g->carry.data(), (size_t)nch * sizeof(ChunkDev),
-                               hipMemcpyHostToDevice, s));
+    const uint32_t nch = (uint32_t)std::min<uint64_t>(g->q_tail - g->q_head, 0xffffffffu);
     HIP_TRY(launch_fill_u32(g->counters_d, 0u, 8, s));
     PropArgs<R> a;
     std::memset(&a, 0, sizeof(a));
@@ -1831,7 +1894,7 @@ cosmica_status launch_slice(ServeGroup* g)
     a.regions = (const RegionDev<R>*)g->regions_d;
     a.orbit = g->orbit_d;
     a.segs = g->segs_d;
-    a.chunks = g->chunks_d;
+    a.chunks = g->ring_d + g->q_head;
     a.n_chunks = nch;
     a.head = g->counters_d + 0;
     a.exP = g->exP;
@@ -1843,6 +1906,8 @@ cosmica_status launch_slice(ServeGroup* g)
     a.suspend = g->susp[g->cur ^ 1];
     a.suspend_count = g->counters_d + 2;
     a.step_budget = slice_steps();
+    a.slice_ticks = slice_ticks(ctx);
+    if (a.step_budget == 0xffffffffu && a.slice_ticks == 0) a.step_budget = 2048u;
     a.job_cancel = g->cancel_d;
     a.job_done = g->done_d;
     a.leftover = g->left_d;
@@ -1863,24 +1928,34 @@ cosmica_status launch_slice(ServeGroup* g)
     const int vgrid = g->grid_var[(a.shaped ? 1 : 0) | (a.energy ? 2 : 0)];
     const int need = (int)(((uint64_t)g->n_resume + (uint64_t)g->block - 1) / (uint64_t)g->block);
     HIP_TRY(launch_model<R>(g->model, a, std::max(vgrid, need), g->block, s));
-    // the host copy of the chunk list must outlive the asynchronous upload
-    HIP_TRY(hipStreamSynchronize(s));
     return COSMICA_OK;
 }
 
 cosmica_status collect_slice(ServeGroup* g)
 {
-    uint32_t c[4];
+    hipStream_t s = g->ctx->serve_stream;
+    uint32_t c[4];  // chunk cursor, resume cursor, parked count, unfinished chunks
     HIP_TRY(hipMemcpy(c, g->counters_d, sizeof(c), hipMemcpyDeviceToHost));
     // every parked particle of the previous slice was taken up (the slice
     // launched at least one lane per parked particle)
     if (c[1] < g->n_resume) return COSMICA_EDEVICE;
-    const uint32_t head = std::min(c[0], g->n_chunks_last);
-    std::vector<ChunkDev> next(c[3]);
-    if (c[3]) HIP_TRY(hipMemcpy(next.data(), g->left_d, c[3] * sizeof(ChunkDev),
-                                hipMemcpyDeviceToHost));
-    next.insert(next.end(), g->carry.begin() + head, g->carry.end());
-    g->carry.swap(next);
+    g->q_head += std::min(c[0], g->n_chunks_last);
+    // chunks waves held unfinished go back in front of the queue (they were
+    // issued from this slice's part of it, so the room before q_head is free),
+    // except those of cancelled requests
+    if (c[3]) {
+        std::vector<ChunkDev> left(c[3]), keep;
+        HIP_TRY(hipMemcpy(left.data(), g->left_d, c[3] * sizeof(ChunkDev), hipMemcpyDeviceToHost));
+        for (const ChunkDev& ch : left)
+            if (!g->slot_cancelled[ch.seg / ServeGroup::kBinsPerSlot]) keep.push_back(ch);
+        if (keep.size() > g->q_head) return COSMICA_EDEVICE;
+        g->q_head -= keep.size();
+        if (!keep.empty()) {
+            HIP_TRY(hipMemcpyAsync(g->ring_d + g->q_head, keep.data(), keep.size() * sizeof(ChunkDev),
+                                   hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+    }
     g->n_resume = c[2];
     g->cur ^= 1;
     return COSMICA_OK;
@@ -1967,7 +2042,8 @@ void serve_loop(cosmica_ctx* ctx)
         for (int m = 0; m < 2; ++m)
             for (int q = 0; q < 2; ++q) {
                 ServeGroup* g = ctx->groups[m][q].get();
-                if (g && (!g->resident.empty() || g->n_resume || !g->releasing.empty()))
+                if (g && (!g->resident.empty() || g->n_resume || !g->releasing.empty() ||
+                          g->q_head < g->q_tail))
                     active.push_back(g);
             }
         if (active.empty()) {
@@ -1983,13 +2059,9 @@ void serve_loop(cosmica_ctx* ctx)
                     if (hipMemcpy(g->cancel_d + q->slot, &one, 4, hipMemcpyHostToDevice) !=
                         hipSuccess)
                         ctx->serve_error = COSMICA_EDEVICE;
-                    const uint32_t s0 = (uint32_t)q->slot * ServeGroup::kBinsPerSlot;
-                    const uint32_t s1 = s0 + (uint32_t)q->job.rig.size();
-                    g->carry.erase(std::remove_if(g->carry.begin(), g->carry.end(),
-                                                  [&](const ChunkDev& c) {
-                                                      return c.seg >= s0 && c.seg < s1;
-                                                  }),
-                                   g->carry.end());
+                    // its queued chunks are dropped as they are issued (the
+                    // kernel skips particles of cancelled jobs)
+                    g->slot_cancelled[q->slot] = 1;
                     q->cancel_sent = true;
                     q->state = 2;
                     q->status = COSMICA_ECANCELED;
@@ -2022,12 +2094,19 @@ void serve_loop(cosmica_ctx* ctx)
                 ok = false;
                 break;
             }
-            for (Req* q : g->releasing) {
-                uint32_t zero = 0;
-                (void)hipMemcpy(g->cancel_d + q->slot, &zero, 4, hipMemcpyHostToDevice);
-                release(g, q);
+            // a cancelled request's slot and records are freed once the queue has
+            // issued all its chunks and a slice has dropped its parked particles
+            for (auto it = g->releasing.begin(); it != g->releasing.end();) {
+                Req* q = *it;
+                if (g->q_head >= q->ring_end) {
+                    uint32_t zero = 0;
+                    (void)hipMemcpy(g->cancel_d + q->slot, &zero, 4, hipMemcpyHostToDevice);
+                    release(g, q);
+                    it = g->releasing.erase(it);
+                } else {
+                    ++it;
+                }
             }
-            g->releasing.clear();
             for (auto it = g->resident.begin(); it != g->resident.end();) {
                 Req* q = *it;
                 if (done[q->slot] >= q->job.total) {
@@ -2171,7 +2250,7 @@ void cosmica_destroy(cosmica_ctx* ctx)
     for (int m = 0; m < 2; ++m)
         for (int q = 0; q < 2; ++q) {
             ServeGroup* g = ctx->groups[m][q].get();
-            if (g && g->chunks_block) dfree(ctx, g->chunks_block, (size_t)g->chunks_cap * sizeof(ChunkDev));
+            if (g && g->ring_d) dfree(ctx, g->ring_d, g->ring_cap * sizeof(ChunkDev));
             ctx->groups[m][q].reset();
         }
     if (ctx->serve_stream) (void)hipStreamDestroy(ctx->serve_stream);

@@ -4,9 +4,12 @@ metadata of a device-only compile (no GPU needed).
 The step loop keeps the particle state and the job constants in VGPRs, so a
 spill to scratch or a register count past an occupancy step shows up in
 throughput at once.  The budget: no kernel spills; the binary32 3D
-propagation kernels stay at or below 102 VGPRs (5 waves per SIMD of 512
-registers) and at or below 128 with the energy form (4 waves); the radial
-binary32 kernels at or below 102.
+propagation kernels whose launch shares one Philox key (the batched path)
+stay at or below 102 VGPRs (5 waves per SIMD of 512 registers); those with a
+key per lane (serving, where each request has its own seed) hold a
+scalar-key and a per-lane-key copy of the step loop and stay at or below 128
+(4 waves: measured faster than forcing 5, which costs instructions); the
+energy form at or below 128; the radial binary32 kernels at or below 102.
 """
 import os
 import re
@@ -41,13 +44,14 @@ def kernels(tmp_path_factory):
     return found
 
 
-def _propagate(kernels, real, model_3d, energy=None):
+def _propagate(kernels, real, model_3d, energy=None, shared_key=None):
     # k_propagate<R, M3D, UKEY, SHAPED, ENERGY>: mangled flags Lb0/Lb1 in that order
-    pat = re.compile(r"k_propagateI%sLb%dELb[01]ELb[01]ELb([01])E" % (real, int(model_3d)))
+    pat = re.compile(r"k_propagateI%sLb%dELb([01])ELb[01]ELb([01])E" % (real, int(model_3d)))
     out = {}
     for name, v in kernels.items():
         m = pat.search(name)
-        if m and (energy is None or int(m.group(1)) == int(energy)):
+        if (m and (energy is None or int(m.group(2)) == int(energy)) and
+                (shared_key is None or int(m.group(1)) == int(shared_key))):
             out[name] = v
     return out
 
@@ -59,10 +63,17 @@ def test_no_kernel_spills(kernels):
 
 
 def test_binary32_3d_propagation_keeps_five_waves(kernels):
-    k = _propagate(kernels, "f", True, energy=False)
-    assert len(k) == 4
+    k = _propagate(kernels, "f", True, energy=False, shared_key=True)
+    assert len(k) == 2
     for name, (vgpr, _) in k.items():
         assert vgpr <= 102, f"{name}: {vgpr} VGPRs (5 waves/SIMD need <= 102)"
+
+
+def test_binary32_3d_per_lane_key_keeps_four_waves(kernels):
+    k = _propagate(kernels, "f", True, energy=False, shared_key=False)
+    assert len(k) == 2
+    for name, (vgpr, _) in k.items():
+        assert vgpr <= 128, f"{name}: {vgpr} VGPRs (4 waves/SIMD need <= 128)"
 
 
 def test_binary32_energy_form_keeps_four_waves(kernels):
