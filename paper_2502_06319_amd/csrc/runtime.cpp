@@ -74,6 +74,22 @@ struct JobCopy {
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
+// The fields of a job the device tables are made from: a view of either a
+// caller's cosmica_job or a JobCopy, so tables can be made without a copy.
+struct JobHead {
+    const cosmica_helio* helio;
+    const cosmica_species* species;
+    uint64_t seed;
+    uint32_t tag, cap, n_orbit;
+    int formulation;
+};
+
+JobHead head_of(const cosmica_job& j)
+{
+    return JobHead{j.helio, j.species, j.seed, j.job_tag,
+                   j.step_cap == 0 ? kDefaultStepCap : j.step_cap, j.n_orbit, j.formulation};
+}
+
 // A point strictly inside the heliopause (the squashed surface of cosmica.h
 // for a 3D heliosphere with a nose distance, else the sphere r_boundary_au).
 bool inside_heliopause(const cosmica_helio& h, double r, double th, double ph)
@@ -198,12 +214,18 @@ JobCopy copy_job(const cosmica_job* j)
     return c;
 }
 
+JobHead head_of(const JobCopy& c)
+{
+    return JobHead{&c.helio, &c.species, c.seed, c.tag, c.cap, (uint32_t)(c.orbit.size() / 3),
+                   c.formulation};
+}
+
 // Physical inputs -> device constants in AU, s, GV.
 template <typename R>
-void make_tables(const JobCopy& jc, JobDev<R>* J, RegionDev<R>* reg, LisDev* lis)
+void make_tables(const JobHead& jc, JobDev<R>* J, RegionDev<R>* reg, LisDev* lis)
 {
-    const cosmica_helio& h = jc.helio;
-    const cosmica_species& s = jc.species;
+    const cosmica_helio& h = *jc.helio;
+    const cosmica_species& s = *jc.species;
     std::memset(J, 0, sizeof(*J));
     J->seed_lo = (uint32_t)(jc.seed & 0xffffffffu);
     J->seed_hi = (uint32_t)(jc.seed >> 32);
@@ -225,7 +247,7 @@ void make_tables(const JobCopy& jc, JobDev<R>* J, RegionDev<R>* reg, LisDev* lis
     J->ts_d2 = hs ? h.ts_tail_au - h.ts_nose_au : 0.0;
     J->ts_prod = hs ? h.ts_nose_au * h.ts_tail_au : 0.0;
     J->shaped = (hs || rb_nose != h.r_boundary_au) ? 1 : 0;
-    J->n_orbit = (uint32_t)(jc.orbit.size() / 3);
+    J->n_orbit = jc.n_orbit;
     J->orbit_off = 0;  // set where the positions are placed
     J->energy = jc.formulation == 1 ? 1 : 0;
     J->mass = s.mass_gev;
@@ -443,12 +465,11 @@ struct DevSet {
 // species x 30 bins, seed 42); on an independent draw of that workload
 // (seed 43) the estimate ranks the bins with a Spearman correlation of 0.93.
 // A wrong estimate costs time only: results do not depend on the queue order.
-double expected_steps(const JobCopy& jc, double P0)
+double expected_steps(const cosmica_helio& h, const cosmica_species& sp, double P0)
 {
-    const cosmica_helio& h = jc.helio;
     if (h.model != COSMICA_MODEL_3D) return 1.0;
     const double lp = std::log(P0);
-    const int sq = jc.species.charge > 0 ? 1 : -1;
+    const int sq = sp.charge > 0 ? 1 : -1;
     if (h.drift == 1 && h.hcs == 1 && sq * h.polarity < 0) {
         double tilt = 0.0;
         for (int k = 0; k < h.n_regions; ++k) tilt += h.tilt_deg[k];
@@ -587,7 +608,7 @@ cosmica_status upload_tables(cosmica_plan* p)
     std::vector<LisDev> lh(nj);
     std::vector<OrbitDev> oh;
     for (size_t j = 0; j < nj; ++j) {
-        make_tables<R>(p->jobs[j], &jh[j], &rh[j * kRegionStride], &lh[j]);
+        make_tables<R>(head_of(p->jobs[j]), &jh[j], &rh[j * kRegionStride], &lh[j]);
         jh[j].orbit_off = (uint32_t)oh.size();
         const std::vector<double>& o = p->jobs[j].orbit;
         for (size_t k = 0; k + 2 < o.size(); k += 3) oh.push_back(OrbitDev{o[k], o[k + 1], o[k + 2], 0.0});
@@ -616,52 +637,97 @@ cosmica_status upload_tables(cosmica_plan* p)
     return COSMICA_OK;
 }
 
+// Device buffers of one propagation + reduction pass (a plan's, or the static
+// array's for cosmica_run_static).
+struct PassDev {
+    const void* jobs;
+    const void* regions;
+    const OrbitDev* orbit;
+    const SegmentDev* segs;
+    const ChunkDev* chunks[2];  // the refill queues of the radial and 3D groups
+    uint32_t n_chunks[2];
+    uint64_t model_particles[2];
+    uint32_t* counters;  // [head0, head1, resume_head, suspend_count, leftover_count]
+    double *exP, *exT, *exL, *exR, *exTh, *exPh;
+    uint32_t* exNF;
+    bool uniform_key, shaped, energy;
+    uint64_t key;
+    int prec;
+};
+
 template <typename R>
-cosmica_status execute_prop(cosmica_plan* p)
+cosmica_status execute_prop(cosmica_ctx* ctx, const PassDev& d)
 {
-    cosmica_ctx* ctx = p->ctx;
     for (int model = 0; model < 2; ++model) {
-        const uint32_t nch = (uint32_t)p->chunks_h[model].size();
+        const uint32_t nch = d.n_chunks[model];
         if (nch == 0) continue;
-        const cosmica_launch& L = ctx->launch[model][p->prec];
+        const cosmica_launch& L = ctx->launch[model][d.prec];
         PropArgs<R> a;
         std::memset(&a, 0, sizeof(a));
-        a.jobs = (const JobDev<R>*)p->jobs_d;
-        a.regions = (const RegionDev<R>*)p->regions_d;
-        a.orbit = p->orbit_d;
-        a.segs = p->segs_d;
-        a.chunks = p->chunks_d[model];
+        a.jobs = (const JobDev<R>*)d.jobs;
+        a.regions = (const RegionDev<R>*)d.regions;
+        a.orbit = d.orbit;
+        a.segs = d.segs;
+        a.chunks = d.chunks[model];
         a.n_chunks = nch;
-        a.head = p->counters_d + model;
-        a.exP = p->exP;
-        a.exT = p->exT;
-        a.exNF = p->exNF;
-        a.exR = p->exR;
-        a.exTh = p->exTh;
-        a.exPh = p->exPh;
+        a.head = d.counters + model;
+        a.exP = d.exP;
+        a.exT = d.exT;
+        a.exNF = d.exNF;
+        a.exR = d.exR;
+        a.exTh = d.exTh;
+        a.exPh = d.exPh;
         a.resume = nullptr;
         a.n_resume = 0;
-        a.resume_head = p->counters_d + 2;
+        a.resume_head = d.counters + 2;
         a.suspend = nullptr;
-        a.suspend_count = p->counters_d + 3;
+        a.suspend_count = d.counters + 3;
         a.step_budget = 0xffffffffu;
+        a.slice_ticks = 0;
         a.job_cancel = nullptr;
         a.job_done = nullptr;
         a.leftover = nullptr;
-        a.leftover_count = p->counters_d + 4;
-        a.uniform_key = p->uniform_key ? 1u : 0u;
-        a.shaped = p->shaped ? 1u : 0u;
-        a.energy = p->energy ? 1u : 0u;
-        a.exL = p->exL;
-        a.key_lo = (uint32_t)(p->key & 0xffffffffu);
-        a.key_hi = (uint32_t)(p->key >> 32);
-        const int grid =
-            grid_for(ctx, model, p->prec, L, p->model_particles[model], p->shaped, p->energy);
+        a.leftover_count = d.counters + 4;
+        a.uniform_key = d.uniform_key ? 1u : 0u;
+        a.shaped = d.shaped ? 1u : 0u;
+        a.energy = d.energy ? 1u : 0u;
+        a.exL = d.exL;
+        a.key_lo = (uint32_t)(d.key & 0xffffffffu);
+        a.key_hi = (uint32_t)(d.key >> 32);
+        const int grid = grid_for(ctx, model, d.prec, L, d.model_particles[model], d.shaped, d.energy);
         ctx->timings.grid_blocks = grid;
         ctx->timings.block = L.block;
         HIP_TRY(launch_model<R>(model, a, grid, L.block, ctx->stream));
     }
     return COSMICA_OK;
+}
+
+PassDev pass_of(const cosmica_plan* p)
+{
+    PassDev d;
+    d.jobs = p->jobs_d;
+    d.regions = p->regions_d;
+    d.orbit = p->orbit_d;
+    d.segs = p->segs_d;
+    for (int m = 0; m < 2; ++m) {
+        d.chunks[m] = p->chunks_d[m];
+        d.n_chunks[m] = (uint32_t)p->chunks_h[m].size();
+        d.model_particles[m] = p->model_particles[m];
+    }
+    d.counters = p->counters_d;
+    d.exP = p->exP;
+    d.exT = p->exT;
+    d.exL = p->exL;
+    d.exR = p->exR;
+    d.exTh = p->exTh;
+    d.exPh = p->exPh;
+    d.exNF = p->exNF;
+    d.uniform_key = p->uniform_key;
+    d.shaped = p->shaped;
+    d.energy = p->energy;
+    d.key = p->key;
+    d.prec = p->prec;
+    return d;
 }
 
 }  // namespace
@@ -771,7 +837,7 @@ cosmica_status cosmica_plan_create(cosmica_ctx* ctx, const cosmica_job* jobs, in
             ids[model].push_back((uint32_t)p->segs.size());
             p->model_particles[model] += jc.cnt[b];
             p->segs.push_back(s);
-            cost.push_back(expected_steps(jc, jc.rig[b]));
+            cost.push_back(expected_steps(jc.helio, jc.species, jc.rig[b]));
         }
     }
     for (int m = 0; m < 2; ++m) {
@@ -828,8 +894,9 @@ cosmica_status cosmica_plan_execute(cosmica_plan* p, const cosmica_bins_dev* out
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(hipEventRecord(ctx->ev[0], ctx->stream));
     HIP_TRY(launch_fill_u32(p->counters_d, 0u, 8, ctx->stream));
-    cosmica_status st = p->prec == COSMICA_PREC_MIXED ? execute_prop<float>(p)
-                                                       : execute_prop<double>(p);
+    const PassDev d = pass_of(p);
+    cosmica_status st = p->prec == COSMICA_PREC_MIXED ? execute_prop<float>(ctx, d)
+                                                       : execute_prop<double>(ctx, d);
     if (st != COSMICA_OK) return st;
     HIP_TRY(hipEventRecord(ctx->ev[1], ctx->stream));
     ReduceArgs r;
@@ -1188,7 +1255,7 @@ cosmica_status cosmica_probe_coeffs(cosmica_ctx* ctx, const cosmica_job* job,
     if (precision == COSMICA_PREC_FP64) {
         JobDev<double> J;
         std::vector<RegionDev<double>> R(kRegionStride);
-        make_tables<double>(jc, &J, R.data(), &lis);
+        make_tables<double>(head_of(jc), &J, R.data(), &lis);
         JobDev<double>* jd = nullptr;
         RegionDev<double>* rd = nullptr;
         if ((st = m.alloc(&jd, 1)) != COSMICA_OK) return st;
@@ -1199,7 +1266,7 @@ cosmica_status cosmica_probe_coeffs(cosmica_ctx* ctx, const cosmica_job* job,
     } else {
         JobDev<float> J;
         std::vector<RegionDev<float>> R(kRegionStride);
-        make_tables<float>(jc, &J, R.data(), &lis);
+        make_tables<float>(head_of(jc), &J, R.data(), &lis);
         JobDev<float>* jd = nullptr;
         RegionDev<float>* rd = nullptr;
         if ((st = m.alloc(&jd, 1)) != COSMICA_OK) return st;
@@ -1242,7 +1309,7 @@ cosmica_status cosmica_probe_locate(cosmica_ctx* ctx, const cosmica_job* job,
     if (precision == COSMICA_PREC_FP64) {
         JobDev<double> J;
         std::vector<RegionDev<double>> R(kRegionStride);
-        make_tables<double>(jc, &J, R.data(), &lis);
+        make_tables<double>(head_of(jc), &J, R.data(), &lis);
         JobDev<double>* jd = nullptr;
         RegionDev<double>* rg = nullptr;
         if ((st = m.alloc(&jd, 1)) != COSMICA_OK) return st;
@@ -1253,7 +1320,7 @@ cosmica_status cosmica_probe_locate(cosmica_ctx* ctx, const cosmica_job* job,
     } else {
         JobDev<float> J;
         std::vector<RegionDev<float>> R(kRegionStride);
-        make_tables<float>(jc, &J, R.data(), &lis);
+        make_tables<float>(head_of(jc), &J, R.data(), &lis);
         JobDev<float>* jd = nullptr;
         RegionDev<float>* rg = nullptr;
         if ((st = m.alloc(&jd, 1)) != COSMICA_OK) return st;
@@ -1778,7 +1845,7 @@ cosmica_status upload_slot(ServeGroup* g, Req* q)
     JobDev<R> J;
     RegionDev<R> reg[kRegionStride];
     LisDev lis;
-    make_tables<R>(q->job, &J, reg, &lis);
+    make_tables<R>(head_of(q->job), &J, reg, &lis);
     hipStream_t s = g->ctx->serve_stream;
     const int slot = q->slot;
     J.orbit_off = (uint32_t)slot * COSMICA_MAX_ORBIT;
@@ -1864,7 +1931,7 @@ cosmica_status admit(cosmica_ctx* ctx)
         const cosmica_launch& L = ctx->launch[q->model][q->prec];
         std::vector<double> cost(g->segs_h.size(), 0.0);
         for (size_t b = 0; b < q->job.rig.size(); ++b)
-            cost[s0 + b] = expected_steps(q->job, q->job.rig[b]);
+            cost[s0 + b] = expected_steps(q->job.helio, q->job.species, q->job.rig[b]);
         std::vector<ChunkDev> chunks;
         make_chunks(g->segs_h, ids, L.chunk, L.order, &chunks, &cost);
         cosmica_status st = q->prec == 1 ? upload_slot<float>(g, q) : upload_slot<double>(g, q);
