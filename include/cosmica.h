@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define COSMICA_ABI_VERSION 4
+#define COSMICA_ABI_VERSION 5
 #define COSMICA_MAX_REGIONS 15 /* radial shells of the inner heliosphere (Sec. II.B) */
 #define COSMICA_REGION_HELIOSHEATH 15 /* region index of the heliosheath */
 #define COSMICA_NHIST 129      /* 128 bins of log10(P_ex/P0) over [0,3) + overflow */
@@ -48,7 +48,8 @@ typedef enum {
     COSMICA_EBUSY = -4,     /* serving queue full */
     COSMICA_ECANCELED = -5, /* the request was cancelled */
     COSMICA_ESTEPCAP = -6,  /* warning: results written, some particles hit the step cap */
-    COSMICA_ENOTFOUND = -7  /* unknown ticket */
+    COSMICA_ENOTFOUND = -7, /* unknown ticket */
+    COSMICA_ESCRATCH = -8   /* cosmica_run_static: the work does not fit its static array */
 } cosmica_status;
 
 typedef enum { COSMICA_MODEL_1D = 0, COSMICA_MODEL_3D = 1 } cosmica_model;
@@ -308,6 +309,29 @@ cosmica_status cosmica_plan_exit_range(cosmica_plan* plan, uint32_t n_hist, doub
                                        uint32_t* hist);
 
 void cosmica_plan_destroy(cosmica_plan* plan);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): cosmica_run
+ * with every device buffer -- job and region tables, work queue, exit records,
+ * per-bin results -- carved from one array of COSMICA_STATIC_BYTES that the
+ * library holds on each GPU it runs on, from the first cosmica_create on that
+ * GPU until the process ends.  The call allocates no memory, on the device or
+ * the host (its host staging is set aside by cosmica_create).  Arguments,
+ * results (bit for bit) and errors are those of cosmica_run; in addition
+ * COSMICA_ESCRATCH, before anything is written, when the work exceeds the
+ * limits: n_jobs <= COSMICA_STATIC_MAX_JOBS, total bins <=
+ * COSMICA_STATIC_MAX_BINS, orbit positions of all jobs <=
+ * COSMICA_STATIC_MAX_ORBIT, and the buffers within the array (about 20 B per
+ * particle, 28 B in the energy form, 80 B more when exits are requested, plus
+ * ~600 B per bin and ~1.4 KB per job).  The array keeps the last call's
+ * contents; calls on one GPU share it and would race, so the library runs
+ * them one at a time (a call waits for the previous one to return). */
+#define COSMICA_STATIC_BYTES 134217728ull /* 128 MiB per GPU */
+#define COSMICA_STATIC_MAX_JOBS 256
+#define COSMICA_STATIC_MAX_BINS 8192
+#define COSMICA_STATIC_MAX_ORBIT 4096
+cosmica_status cosmica_run_static(cosmica_ctx* ctx, const cosmica_job* jobs, int32_t n_jobs,
+                                  cosmica_precision precision, cosmica_result* results);
 
 /* Launch shape used for (model, precision); the defaults come from the
  * autotuner cache when one was loaded, else built-in values (256 threads, full

@@ -27,11 +27,16 @@ MAX_JOBS = 1048576
 MAX_REWEIGHT = 4096
 MAX_LIS_KNOTS = 256
 MAX_RANGE_BINS = 4096
+STATIC_BYTES = 134217728
+STATIC_MAX_JOBS = 256
+STATIC_MAX_BINS = 8192
+STATIC_MAX_ORBIT = 4096
 MODEL_1D, MODEL_3D = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 PRECISION = {"fp64": PREC_FP64, "mixed": PREC_MIXED, PREC_FP64: PREC_FP64, PREC_MIXED: PREC_MIXED}
 
 OK, EINVAL, ENOMEM, EDEVICE, EBUSY, ECANCELED, ESTEPCAP, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7
+ESCRATCH = -8
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
 c_u32_p = ctypes.POINTER(ctypes.c_uint32)
@@ -140,6 +145,8 @@ _SIGS = {
                                              c_double_p, c_double_p]),
     "cosmica_plan_exit_range": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, c_double_p,
                                                c_u32_p]),
+    "cosmica_run_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Job), ctypes.c_int32,
+                                          ctypes.c_int, ctypes.POINTER(Result)]),
     "cosmica_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                           ctypes.POINTER(Launch)]),
     "cosmica_get_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
@@ -408,6 +415,19 @@ class Engine:
         self.last_status = _check(load().cosmica_run(self.handle, jarr, len(packs),
                                                      PRECISION[precision], rarr),
                                   "run", ok=(OK, ESTEPCAP))
+        return [r.as_dict() for r in res]
+
+    def run_static(self, jobs, precision="mixed", exits: bool = False) -> list[dict]:
+        """cosmica_run_static: run without allocating device memory (buffers in
+        the library's static per-GPU array; raises with ESCRATCH past its limits)."""
+        jobs = [jobs] if isinstance(jobs, dict) else list(jobs)
+        packs = [_JobPack(j) for j in jobs]
+        res = [_ResultPack(p.n_bins, p.total, exits) for p in packs]
+        jarr = (Job * len(packs))(*[p.job for p in packs])
+        rarr = (Result * len(res))(*[r.c for r in res])
+        self.last_status = _check(load().cosmica_run_static(self.handle, jarr, len(packs),
+                                                            PRECISION[precision], rarr),
+                                  "run_static", ok=(OK, ESTEPCAP))
         return [r.as_dict() for r in res]
 
     def plan(self, jobs, precision="mixed", exits: bool = False) -> Plan:

@@ -176,6 +176,14 @@ struct RangeArgs {
     uint32_t* hist;  // total_bins * n_hist
 };
 
+// An exit record in the layout of cosmica_exit, so records can be copied
+// straight into a caller's array.
+struct ExitRecDev {
+    double P, t, r, th, ph;
+    uint32_t n, flags;
+    double loss;
+};
+
 // Launchers (kernels.hip).
 hipError_t launch_propagate_3d_mixed(const PropArgs<float>& a, int grid, int block, hipStream_t s);
 hipError_t launch_propagate_3d_fp64(const PropArgs<double>& a, int grid, int block, hipStream_t s);
@@ -187,6 +195,10 @@ hipError_t launch_reduce(const ReduceArgs& a, uint32_t n_segs, hipStream_t s);
 hipError_t launch_reweight(const ReweightArgs& a, uint32_t n_segs, hipStream_t s);
 hipError_t launch_exit_range(const RangeArgs& a, uint32_t n_segs, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint32_t n, hipStream_t s);
+// Exit records [0, n) from the per-field arrays (L, R, Th, Ph may be null: 0).
+hipError_t launch_pack_exits(const double* P, const double* T, const uint32_t* NF,
+                             const double* L, const double* R, const double* Th,
+                             const double* Ph, uint32_t n, ExitRecDev* out, hipStream_t s);
 
 // Diagnostics: raw Philox words and normals for counters (i, c1, c2, c3),
 // i = c0 .. c0+n-1; coefficients at given points.

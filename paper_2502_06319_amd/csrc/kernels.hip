@@ -1253,6 +1253,34 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint32_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+__global__ void k_pack_exits(const double* P, const double* T, const uint32_t* NF,
+                             const double* L, const double* R, const double* Th,
+                             const double* Ph, uint32_t n, ExitRecDev* out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    ExitRecDev e;
+    e.P = P[i];
+    e.t = T[i];
+    e.r = R ? R[i] : 0.0;
+    e.th = Th ? Th[i] : 0.0;
+    e.ph = Ph ? Ph[i] : 0.0;
+    e.n = NF[i] & ((1u << kFlagShift) - 1u);
+    e.flags = NF[i] >> kFlagShift;
+    e.loss = L ? L[i] : 0.0;
+    out[i] = e;
+}
+
+hipError_t launch_pack_exits(const double* P, const double* T, const uint32_t* NF,
+                             const double* L, const double* R, const double* Th,
+                             const double* Ph, uint32_t n, ExitRecDev* out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_exits, dim3((n + 255) / 256), dim3(256), 0, s, P, T, NF, L, R, Th,
+                       Ph, n, out);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Diagnostics.
 // ---------------------------------------------------------------------------

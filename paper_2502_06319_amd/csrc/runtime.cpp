@@ -32,6 +32,11 @@ using namespace cosmica;
 
 namespace {
 
+static_assert(sizeof(ExitRecDev) == sizeof(cosmica_exit) &&
+                  offsetof(ExitRecDev, n) == offsetof(cosmica_exit, n) &&
+                  offsetof(ExitRecDev, loss) == offsetof(cosmica_exit, loss),
+              "device exit records use the layout of cosmica_exit");
+
 // Physical constants of the unit conversion (AU: IAU 2012).
 constexpr double kAuCm = 1.495978707e13;
 constexpr double kAuKm = 1.495978707e8;
@@ -190,12 +195,13 @@ cosmica_status validate(const cosmica_job* j)
 
 // A job whose heliopause is squashed or that has a heliosheath needs the
 // propagation kernel that tests those surfaces.
-bool job_shaped(const JobCopy& jc)
+bool helio_shaped(const cosmica_helio& h)
 {
-    const cosmica_helio& h = jc.helio;
     return h.model == COSMICA_MODEL_3D &&
            (h.heliosheath == 1 || (h.r_boundary_nose_au > 0.0 && h.r_boundary_nose_au != h.r_boundary_au));
 }
+
+bool job_shaped(const JobCopy& jc) { return helio_shaped(jc.helio); }
 
 JobCopy copy_job(const cosmica_job* j)
 {
@@ -327,6 +333,58 @@ struct Pool;
 struct Req;
 struct ServeGroup;
 
+// The device array behind cosmica_run_static: file scope, so each GPU the
+// library runs on holds one copy from module load until the process ends.
+// In host code its name only stands in for the symbol: every use goes through
+// the address hipGetSymbolAddress returned for the device (static_base).
+static __device__ __align__(256) unsigned char scratch[COSMICA_STATIC_BYTES];
+
+namespace {
+
+constexpr int kStaticDevices = 64;
+std::mutex g_static_mu;                         // guards g_static_base
+void* g_static_base[kStaticDevices] = {};       // device address of `scratch`, per device
+std::mutex g_static_call_mu[kStaticDevices];    // one cosmica_run_static per device at a time
+
+// Looks up the array's address on `device` once (the device must be current).
+void static_setup(int device)
+{
+    if (device < 0 || device >= kStaticDevices) return;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_base[device] != nullptr) return;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p != nullptr)
+        g_static_base[device] = p;
+    else
+        (void)hipGetLastError();  // cosmica_run_static then reports COSMICA_EDEVICE
+}
+
+void* static_base(int device)
+{
+    if (device < 0 || device >= kStaticDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    return g_static_base[device];
+}
+
+// Host staging of cosmica_run_static, set aside when a context is created so
+// that the call itself allocates nothing (~1.9 MB).
+constexpr uint32_t kStaticMaxChunks = 65536;
+struct StaticHost {
+    alignas(64) unsigned char jobs[COSMICA_STATIC_MAX_JOBS * sizeof(JobDev<double>)];
+    alignas(64) unsigned char regions[COSMICA_STATIC_MAX_JOBS * kRegionStride *
+                                      sizeof(RegionDev<double>)];
+    LisDev lis[COSMICA_STATIC_MAX_JOBS];
+    uint32_t seg_first[COSMICA_STATIC_MAX_JOBS];
+    OrbitDev orbit[COSMICA_STATIC_MAX_ORBIT];
+    SegmentDev segs[COSMICA_STATIC_MAX_BINS];
+    double cost[COSMICA_STATIC_MAX_BINS];
+    uint32_t ids[COSMICA_STATIC_MAX_BINS];
+    uint32_t ncap[COSMICA_STATIC_MAX_BINS];
+    ChunkDev chunks[kStaticMaxChunks];
+};
+
+}  // namespace
+
 struct cosmica_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -361,6 +419,7 @@ struct cosmica_ctx {
     std::unique_ptr<ServeGroup> groups[2][2];
     hipStream_t serve_stream = nullptr;
     cosmica_status serve_error = COSMICA_OK;
+    std::unique_ptr<StaticHost> stat;  // host staging of cosmica_run_static
     cosmica_ctx() = default;
     ~cosmica_ctx();  // defined once the serving types are complete
 };
@@ -747,6 +806,7 @@ const char* cosmica_strerror(cosmica_status s)
     case COSMICA_ECANCELED: return "request cancelled";
     case COSMICA_ESTEPCAP: return "some particles reached the step cap";
     case COSMICA_ENOTFOUND: return "unknown ticket";
+    case COSMICA_ESCRATCH: return "the work exceeds the static array of cosmica_run_static";
     }
     return "unknown status";
 }
@@ -777,6 +837,11 @@ cosmica_status cosmica_create(cosmica_ctx** out, int device, uint64_t hbm_budget
         ctx->wall_khz = 0;  // slices then end by their step budget only
     }
     ctx->arch = prop.gcnArchName;
+    // set-up of cosmica_run_static: its host staging, and (once per device)
+    // the device address of its array
+    ctx->stat.reset(new (std::nothrow) StaticHost);
+    if (!ctx->stat) return COSMICA_ENOMEM;
+    static_setup(device);
     size_t freeb = 0, totalb = 0;
     HIP_TRY(hipMemGetInfo(&freeb, &totalb));
     ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)freeb);
@@ -1174,6 +1239,280 @@ cosmica_status cosmica_run(cosmica_ctx* ctx, const cosmica_job* jobs, int32_t n_
     }
     cosmica_plan_destroy(p);
     return st;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Byte offsets of cosmica_run_static's buffers within the static array.
+struct StaticLayout {
+    size_t jobs, regions, lis, orbit, segs, chunks, counters;
+    size_t exP, exT, exNF, exL, exR, exTh, exPh, exits;
+    size_t hist, flux, se, mt, steps, ncap, nnan;
+    size_t total;
+};
+
+StaticLayout static_layout(int prec, uint32_t n_jobs, uint32_t n_bins, uint32_t n_orbit,
+                           uint32_t n_chunks, uint64_t n, bool energy, bool exits)
+{
+    StaticLayout L;
+    size_t at = 0;
+    auto carve = [&](size_t bytes) {
+        const size_t o = at;
+        at += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    const size_t jb = prec == COSMICA_PREC_MIXED ? sizeof(JobDev<float>) : sizeof(JobDev<double>);
+    const size_t rb = prec == COSMICA_PREC_MIXED ? sizeof(RegionDev<float>) : sizeof(RegionDev<double>);
+    L.jobs = carve(n_jobs * jb);
+    L.regions = carve((size_t)n_jobs * kRegionStride * rb);
+    L.lis = carve(n_jobs * sizeof(LisDev));
+    L.orbit = carve(n_orbit * sizeof(OrbitDev));
+    L.segs = carve(n_bins * sizeof(SegmentDev));
+    L.chunks = carve(n_chunks * sizeof(ChunkDev));
+    L.counters = carve(8 * sizeof(uint32_t));
+    L.exP = carve(n * 8);
+    L.exT = carve(n * 8);
+    L.exNF = carve(n * 4);
+    L.exL = carve(energy ? n * 8 : 0);
+    L.exR = carve(exits ? n * 8 : 0);
+    L.exTh = carve(exits ? n * 8 : 0);
+    L.exPh = carve(exits ? n * 8 : 0);
+    L.exits = carve(exits ? n * sizeof(ExitRecDev) : 0);
+    L.hist = carve((size_t)n_bins * kNHist * 4);
+    L.flux = carve(n_bins * 8);
+    L.se = carve(n_bins * 8);
+    L.mt = carve(n_bins * 8);
+    L.steps = carve(n_bins * 8);
+    L.ncap = carve(n_bins * 4);
+    L.nnan = carve(n_bins * 4);
+    L.total = at;
+    return L;
+}
+
+template <typename R>
+cosmica_status run_static(cosmica_ctx* ctx, const cosmica_job* jobs, uint32_t n_jobs, int prec,
+                          cosmica_result* results)
+{
+    StaticHost& H = *ctx->stat;
+    // sizes of the work
+    uint32_t n_bins = 0, n_orbit = 0;
+    uint64_t total = 0, model_particles[2] = {0, 0};
+    bool energy = false, shaped = false, exits = false, ukey = true;
+    for (uint32_t j = 0; j < n_jobs; ++j) {
+        const cosmica_job& J = jobs[j];
+        n_bins += (uint32_t)J.n_bins;
+        n_orbit += J.n_orbit;
+        for (int b = 0; b < J.n_bins; ++b) {
+            total += J.particles_per_bin[b];
+            model_particles[J.helio->model] += J.particles_per_bin[b];
+        }
+        energy |= J.formulation == 1;
+        shaped |= helio_shaped(*J.helio);
+        exits |= results[j].exits != nullptr;
+        ukey &= J.seed == jobs[0].seed;
+        if (n_bins > COSMICA_STATIC_MAX_BINS || n_orbit > COSMICA_STATIC_MAX_ORBIT)
+            return COSMICA_ESCRATCH;
+    }
+    if (total >= (1ull << 32)) return COSMICA_EINVAL;
+    // segments (jobs x bins) and their expected steps per particle
+    uint32_t off = 0, ns = 0;
+    for (uint32_t j = 0; j < n_jobs; ++j) {
+        const cosmica_job& J = jobs[j];
+        H.seg_first[j] = ns;
+        for (int b = 0; b < J.n_bins; ++b, ++ns) {
+            SegmentDev& g = H.segs[ns];
+            std::memset(&g, 0, sizeof(g));
+            g.P0 = J.rigidity_gv[b];
+            g.job = j;
+            g.bin = J.bin_offset + (uint32_t)b;
+            g.count = J.particles_per_bin[b];
+            g.out_offset = off;
+            off += J.particles_per_bin[b];
+            H.cost[ns] = expected_steps(*J.helio, *J.species, J.rigidity_gv[b]);
+        }
+    }
+    // refill chunks of each model group in the launch's queue order; the chunk
+    // is enlarged where needed to keep the queue within the staging (the
+    // results do not depend on the chunk size)
+    const uint64_t room = kStaticMaxChunks - COSMICA_STATIC_MAX_BINS;
+    uint32_t nc = 0, first[2] = {0, 0}, nch[2] = {0, 0};
+    for (int m = 0; m < 2; ++m) {
+        const cosmica_launch& L = ctx->launch[m][prec];
+        const uint32_t c =
+            (uint32_t)std::max<uint64_t>((uint64_t)std::max(1, L.chunk), (total + room - 1) / room);
+        uint32_t k = 0;
+        for (uint32_t i = 0; i < ns; ++i)
+            if (jobs[H.segs[i].job].helio->model == m) H.ids[k++] = i;
+        const SegmentDev* sg = H.segs;
+        const double* cost = H.cost;
+        if (L.order == 2)
+            std::sort(H.ids, H.ids + k, [&](uint32_t a, uint32_t b) {
+                if (cost[a] != cost[b]) return cost[a] > cost[b];
+                if (sg[a].count != sg[b].count) return sg[a].count > sg[b].count;
+                return a < b;
+            });
+        else if (L.order == 1)
+            std::sort(H.ids, H.ids + k, [&](uint32_t a, uint32_t b) {
+                if (sg[a].count != sg[b].count) return sg[a].count > sg[b].count;
+                return a < b;
+            });
+        first[m] = nc;
+        for (uint32_t i = 0; i < k; ++i) {
+            const uint32_t seg = H.ids[i];
+            for (uint32_t f = 0; f < sg[seg].count; f += c) {
+                ChunkDev& ch = H.chunks[nc++];
+                ch.seg = seg;
+                ch.first = f;
+                ch.count = std::min(c, sg[seg].count - f);
+                ch.pad0 = 0;
+            }
+        }
+        nch[m] = nc - first[m];
+    }
+    const StaticLayout Lo = static_layout(prec, n_jobs, n_bins, n_orbit, nc, total, energy, exits);
+    if (Lo.total > COSMICA_STATIC_BYTES) return COSMICA_ESCRATCH;
+    // device tables
+    JobDev<R>* jh = (JobDev<R>*)H.jobs;
+    RegionDev<R>* rh = (RegionDev<R>*)H.regions;
+    uint32_t o = 0;
+    for (uint32_t j = 0; j < n_jobs; ++j) {
+        make_tables<R>(head_of(jobs[j]), &jh[j], &rh[(size_t)j * kRegionStride], &H.lis[j]);
+        jh[j].orbit_off = o;
+        for (uint32_t k = 0; k < jobs[j].n_orbit; ++k, ++o) {
+            const double* q = jobs[j].orbit + 3 * (size_t)k;
+            H.orbit[o] = OrbitDev{q[0], q[1], q[2], 0.0};
+        }
+    }
+
+    HIP_TRY(hipSetDevice(ctx->device));
+    unsigned char* base = (unsigned char*)static_base(ctx->device);
+    if (base == nullptr) return COSMICA_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_static_call_mu[ctx->device]);
+    hipStream_t st = ctx->stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    auto at = [&](size_t offset) { return (void*)(base + offset); };
+    HIP_TRY(hipMemcpyAsync(at(Lo.jobs), jh, n_jobs * sizeof(JobDev<R>), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(at(Lo.regions), rh, (size_t)n_jobs * kRegionStride * sizeof(RegionDev<R>),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(at(Lo.lis), H.lis, n_jobs * sizeof(LisDev), hipMemcpyHostToDevice, st));
+    if (n_orbit)
+        HIP_TRY(hipMemcpyAsync(at(Lo.orbit), H.orbit, n_orbit * sizeof(OrbitDev),
+                               hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(at(Lo.segs), H.segs, n_bins * sizeof(SegmentDev), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(at(Lo.chunks), H.chunks, nc * sizeof(ChunkDev), hipMemcpyHostToDevice, st));
+    // the array keeps the last call's contents: the queue cursors start at
+    // zero, and momentum-form particles leave the loss records unwritten
+    HIP_TRY(launch_fill_u32((uint32_t*)at(Lo.counters), 0u, 8, st));
+    if (energy) HIP_TRY(launch_fill_u32((uint32_t*)at(Lo.exL), 0u, (uint32_t)(2 * total), st));
+    const double up =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+
+    PassDev d;
+    d.jobs = at(Lo.jobs);
+    d.regions = at(Lo.regions);
+    d.orbit = (const OrbitDev*)at(Lo.orbit);
+    d.segs = (const SegmentDev*)at(Lo.segs);
+    for (int m = 0; m < 2; ++m) {
+        d.chunks[m] = (const ChunkDev*)at(Lo.chunks) + first[m];
+        d.n_chunks[m] = nch[m];
+        d.model_particles[m] = model_particles[m];
+    }
+    d.counters = (uint32_t*)at(Lo.counters);
+    d.exP = (double*)at(Lo.exP);
+    d.exT = (double*)at(Lo.exT);
+    d.exNF = (uint32_t*)at(Lo.exNF);
+    d.exL = energy ? (double*)at(Lo.exL) : nullptr;
+    d.exR = exits ? (double*)at(Lo.exR) : nullptr;
+    d.exTh = exits ? (double*)at(Lo.exTh) : nullptr;
+    d.exPh = exits ? (double*)at(Lo.exPh) : nullptr;
+    d.uniform_key = ukey;
+    d.shaped = shaped;
+    d.energy = energy;
+    d.key = jobs[0].seed;
+    d.prec = prec;
+    HIP_TRY(hipEventRecord(ctx->ev[0], st));
+    cosmica_status s = execute_prop<R>(ctx, d);
+    if (s != COSMICA_OK) return s;
+    HIP_TRY(hipEventRecord(ctx->ev[1], st));
+    ReduceArgs r;
+    std::memset(&r, 0, sizeof(r));
+    r.segs = d.segs;
+    r.lis = (const LisDev*)at(Lo.lis);
+    r.exP = d.exP;
+    r.exT = d.exT;
+    r.exNF = d.exNF;
+    r.exL = d.exL;
+    r.seg_base = 0;
+    r.out_base = 0;
+    r.hist = (uint32_t*)at(Lo.hist);
+    r.flux = (double*)at(Lo.flux);
+    r.flux_se = (double*)at(Lo.se);
+    r.mean_t = (double*)at(Lo.mt);
+    r.steps = (uint64_t*)at(Lo.steps);
+    r.n_capped = (uint32_t*)at(Lo.ncap);
+    r.n_nan = (uint32_t*)at(Lo.nnan);
+    HIP_TRY(launch_reduce(r, n_bins, st));
+    HIP_TRY(hipEventRecord(ctx->ev[2], st));
+    ExitRecDev* ex = (ExitRecDev*)at(Lo.exits);
+    if (exits)
+        HIP_TRY(launch_pack_exits(d.exP, d.exT, d.exNF, d.exL, d.exR, d.exTh, d.exPh,
+                                  (uint32_t)total, ex, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    // results straight into the caller's buffers (a job's bins and particles
+    // are contiguous)
+    const auto t1 = std::chrono::steady_clock::now();
+    HIP_TRY(hipMemcpy(H.ncap, r.n_capped, n_bins * 4, hipMemcpyDeviceToHost));
+    bool capped = false;
+    for (uint32_t j = 0; j < n_jobs; ++j) {
+        const cosmica_result& R_ = results[j];
+        const uint32_t s0 = H.seg_first[j];
+        const size_t nb = (size_t)jobs[j].n_bins;
+        if (R_.hist)
+            HIP_TRY(hipMemcpy(R_.hist, r.hist + (size_t)s0 * kNHist, nb * kNHist * 4,
+                              hipMemcpyDeviceToHost));
+        if (R_.flux) HIP_TRY(hipMemcpy(R_.flux, r.flux + s0, nb * 8, hipMemcpyDeviceToHost));
+        if (R_.flux_se) HIP_TRY(hipMemcpy(R_.flux_se, r.flux_se + s0, nb * 8, hipMemcpyDeviceToHost));
+        if (R_.mean_exit_time_s)
+            HIP_TRY(hipMemcpy(R_.mean_exit_time_s, r.mean_t + s0, nb * 8, hipMemcpyDeviceToHost));
+        if (R_.steps) HIP_TRY(hipMemcpy(R_.steps, r.steps + s0, nb * 8, hipMemcpyDeviceToHost));
+        if (R_.n_nan) HIP_TRY(hipMemcpy(R_.n_nan, r.n_nan + s0, nb * 4, hipMemcpyDeviceToHost));
+        if (R_.n_capped) std::memcpy(R_.n_capped, H.ncap + s0, nb * 4);
+        for (size_t b = 0; b < nb; ++b) capped |= H.ncap[s0 + b] > 0;
+        if (R_.exits) {
+            uint64_t n = 0;
+            for (size_t b = 0; b < nb; ++b) n += jobs[j].particles_per_bin[b];
+            HIP_TRY(hipMemcpy(R_.exits, ex + H.segs[s0].out_offset, n * sizeof(ExitRecDev),
+                              hipMemcpyDeviceToHost));
+        }
+    }
+    ctx->last_steps = r.steps;
+    ctx->last_nsteps = n_bins;
+    ctx->timings_pending = true;
+    ctx->timings.particles = total;
+    ctx->timings.upload_ms = up;
+    ctx->timings.download_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
+    return capped ? COSMICA_ESTEPCAP : COSMICA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cosmica_status cosmica_run_static(cosmica_ctx* ctx, const cosmica_job* jobs, int32_t n_jobs,
+                                  cosmica_precision precision, cosmica_result* results)
+{
+    if (ctx == nullptr || jobs == nullptr || results == nullptr || n_jobs < 1) return COSMICA_EINVAL;
+    if (precision != COSMICA_PREC_FP64 && precision != COSMICA_PREC_MIXED) return COSMICA_EINVAL;
+    for (int j = 0; j < n_jobs && j < COSMICA_MAX_JOBS; ++j)
+        if (validate(&jobs[j]) != COSMICA_OK) return COSMICA_EINVAL;
+    if (n_jobs > COSMICA_STATIC_MAX_JOBS) return COSMICA_ESCRATCH;
+    if (!ctx->stat) return COSMICA_EDEVICE;
+    return precision == COSMICA_PREC_MIXED
+               ? run_static<float>(ctx, jobs, (uint32_t)n_jobs, precision, results)
+               : run_static<double>(ctx, jobs, (uint32_t)n_jobs, precision, results);
 }
 
 cosmica_status cosmica_set_launch(cosmica_ctx* ctx, cosmica_model model,

@@ -40,16 +40,17 @@ def test_library_exports_every_declared_function():
 def test_limits_match_the_header():
     hdr = open(HEADER).read()
     for name in ("MAX_REGIONS", "MAX_STEP_CAP", "MAX_ORBIT", "MAX_JOBS", "MAX_REWEIGHT",
-                 "MAX_LIS_KNOTS", "MAX_RANGE_BINS"):
-        m = re.search(rf"#define COSMICA_{name} (\d+)u?", hdr)
+                 "MAX_LIS_KNOTS", "MAX_RANGE_BINS", "STATIC_BYTES", "STATIC_MAX_JOBS",
+                 "STATIC_MAX_BINS", "STATIC_MAX_ORBIT"):
+        m = re.search(rf"#define COSMICA_{name} (\d+)(?:u|ull)?", hdr)
         assert m and int(m.group(1)) == getattr(C, name), name
 
 
 def test_abi_version_and_strerror():
     lib = C.load()
-    assert lib.cosmica_abi_version() == 4
+    assert lib.cosmica_abi_version() == 5
     for st in (C.OK, C.EINVAL, C.ENOMEM, C.EDEVICE, C.EBUSY, C.ECANCELED, C.ESTEPCAP,
-               C.ENOTFOUND, 123):
+               C.ENOTFOUND, C.ESCRATCH, 123):
         assert isinstance(lib.cosmica_strerror(st), bytes)
 
 
@@ -239,6 +240,7 @@ def test_null_pointers_are_rejected():
     assert lib.cosmica_poll(None, 1, None) == C.EINVAL
     assert lib.cosmica_cancel(None, 1) == C.EINVAL
     assert lib.cosmica_request_state(None, 1, None) == C.EINVAL
+    assert lib.cosmica_run_static(None, None, 0, 0, None) == C.EINVAL
     assert lib.cosmica_tune(None, 0, 0, None) == C.EINVAL
     lib.cosmica_destroy(None)
     lib.cosmica_plan_destroy(None)
