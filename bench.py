@@ -47,10 +47,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "propagate_batched_mixed_traffic.t
 # bin are per particle, not per step.  Hardware transcendentals (rcp, rsq,
 # sqrt, log, exp, sin, cos) issue to their own unit and overlap with this
 # stream, so they are tallied apart and left out of the fraction of peak.
+# The current sheet's 50 include its phase formed and reduced in binary64
+# (multiply, fraction, conversion) and the sheet factor 1 - tanh^2 formed
+# from the tanh's own exponential, which binary32 accuracy there requires.
 OPS_PER_STEP = {
     "3d": {"philox4x32_10": 37, "uniforms": 8, "box_muller": 5, "geometry_and_wind": 8,
            "region_lookup": 4, "beta_kappa": 7, "spiral_weights": 8,
-           "tensor_and_divergence": 8, "drift_prelude": 7, "current_sheet": 46,
+           "tensor_and_divergence": 8, "drift_prelude": 7, "current_sheet": 50,
            "gradient_curvature_drift": 12, "sde_drift": 12, "time_step": 12,
            "tensor_sqrt": 6, "em_update": 20, "reflections": 5, "exit_test": 2},
     "1d": {"philox4x32_10": 37, "uniforms": 4, "box_muller": 2, "region_lookup": 4,

@@ -92,18 +92,19 @@ struct Mth<float> {
         return __builtin_amdgcn_cosf(x * 0.159154943091895336f);
     }
     static __device__ __forceinline__ float atan(float x) { return ::atanf(x); }
-    // tanh x and 1 - tanh^2 x, both from e = e^(-2|x|) in [0, 1]:
-    // tanh|x| = (1 - e) / (1 + e) and 1 - tanh^2 x = 4 e / (1 + e)^2.  The second
-    // keeps its relative accuracy where tanh x -> +-1 (1 - tanh^2 would cancel
-    // there: at tanh x = 0.9999997 binary32 leaves it ~20 % off); |x| = inf
-    // gives exactly +-1 and 0.
-    static __device__ __forceinline__ void tanh_sech2(float x, float* t, float* s2)
+    // tanh x and (1 - tanh^2 x) / 4 for x = x4 / 4, both from e = e^(-2|x|) in
+    // [0, 1]: tanh|x| = (1 - e) / (1 + e) and 1 - tanh^2 x = 4 e / (1 + e)^2.  The
+    // second keeps its relative accuracy where tanh x -> +-1 (1 - tanh^2 would
+    // cancel there: at tanh x = 0.9999997 binary32 leaves it ~20 % off);
+    // |x4| = inf gives exactly +-1 and 0.  The caller's x4 carries the 4 that
+    // the second result drops (one multiply fewer).
+    static __device__ __forceinline__ void tanh_sech2_x4(float x4, float* t, float* s2_4)
     {
-        const float e = __builtin_amdgcn_exp2f(-2.88539008177792681f * fabsf(x));
+        const float e = __builtin_amdgcn_exp2f(-0.721347520444482f * fabsf(x4));
         const float q = __builtin_amdgcn_rcpf(1.0f + e);
         const float eq = e * q;
-        *t = __builtin_copysignf(q - eq, x);
-        *s2 = (4.0f * eq) * q;
+        *t = __builtin_copysignf(q - eq, x4);
+        *s2_4 = eq * q;
     }
     // x - 2 pi floor(x / 2 pi): in [0, 2 pi) up to one rounding
     static __device__ __forceinline__ float fmod2pi(float x)
@@ -125,8 +126,9 @@ struct Mth<double> {
     }
     static __device__ __forceinline__ double cos_rad(double x) { return ::cos(x); }
     static __device__ __forceinline__ double atan(double x) { return ::atan(x); }
-    static __device__ __forceinline__ void tanh_sech2(double x, double* t, double* s2)
+    static __device__ __forceinline__ void tanh_sech2_x4(double x, double* t, double* s2)
     {
+        // binary64: x is the argument itself (no factor 4; see load_job)
         *t = ::tanh(x);
         *s2 = 1.0 - *t * *t;
     }
@@ -231,13 +233,15 @@ __device__ __forceinline__ JobReg<R> load_job(const JobDev<R>& J)
     o.sqf2 = J.sqf2;
     o.twof = J.twof;
     o.gcoef = J.gcoef;
-    o.hb = J.hb;
+    // binary32: 1/Delta carries a factor 4 that the sheet factor drops
+    // (Mth<float>::tanh_sech2_x4)
+    o.hb = std::is_same<R, float>::value ? J.hb * (R)4 : J.hb;
     o.abs_z = J.abs_z;
     o.mass2 = J.mass2;
     o.sqA = J.sqA;
     o.dt_max = J.dt_max;
     o.diff_frac = J.diff_frac;
-    o.adv_frac = J.adv_frac;
+    o.adv_frac = J.adv_frac > (R)0 ? J.adv_frac : (R)__builtin_huge_valf();
     o.rb = J.rb;
     o.inv_shell = J.inv_shell;
     o.rb_tail = J.rb_tail;
@@ -379,10 +383,11 @@ __device__ __forceinline__ void coeffs3d(const JobReg<R>& J, const RegionDev<R>&
             const R y = g.tana * sc;
             const R u = lam - M::atan(y);
             // 1/Delta = r |B| / (2 r_L coefficient P), |B| = br0 sqrt(1+Gamma^2) / r^2
+            // (in binary32 times 4, and Hp below over 4: their product is exact)
             const R invDelta = (J.hb * M::sqrt((R)1.0 + Gam2)) * (invr * M::rcp(P));
             // without the sheet the argument is +inf: Hw = 1, Hp = 0, no sheet drift
             R Hp;
-            M::tanh_sech2(u * invDelta + J.sheet_off, &Hw, &Hp);
+            M::tanh_sech2_x4(u * invDelta + J.sheet_off, &Hw, &Hp);
             const R cs = (-g.tana * cc) * M::rcp(y * y + (R)1.0);
             const R gr = cs * g.om_vs;  // d theta_cs / dr
             const R gph = cs * irs;     // (1/(r sin)) d theta_cs / dphi
@@ -405,18 +410,18 @@ __device__ __forceinline__ void coeffs3d(const JobReg<R>& J, const RegionDev<R>&
     c.Ap = (dKrp - vdp) * irs;
     c.AP = ((V * P) * invr) * (R)(2.0 / 3.0);
     c.V = V;
-    // time step: min(dt_max, f_diff r^2 / k_par, f_adv r / |A_det|)
+    // time step: min(dt_max, f_diff r^2 / k_par, f_adv r / |A_det|); fmin keeps
+    // the running value when a limit is NaN, like the comparison d < dt would
     R dt = J.dt_max;
     const R d1 = (J.diff_frac * rr) * M::rcp(kpar);
-    dt = d1 < dt ? d1 : dt;
-    if (J.adv_frac > (R)0) {
+    dt = fmin(d1, dt);
+    {
+        // adv_frac is +inf when the limit is off, and a2 = 0 gives d2 = inf too
         const R at = r * c.At;
         const R ap = (r * st) * c.Ap;
         const R a2 = c.Ar * c.Ar + (at * at + ap * ap);
-        if (a2 > (R)0) {
-            const R d2 = (J.adv_frac * r) * M::rsqrt(a2);
-            dt = d2 < dt ? d2 : dt;
-        }
+        const R d2 = (J.adv_frac * r) * M::rsqrt(a2);
+        dt = fmin(d2, dt);
     }
     c.dt = dt;
     const R tK = Krr + Krr;
@@ -585,7 +590,7 @@ __device__ __forceinline__ void step1d(const JobReg<R>& J, const RegionRef<R> re
     const R AP = (R)(2.0 / 3.0) * V * P * invr;
     R dt = J.dt_max;
     const R d1 = J.diff_frac * r * r * M::rcp(kap);
-    dt = d1 < dt ? d1 : dt;
+    dt = fmin(d1, dt);
     const R sdt = M::sqrt(dt);
     double r1 = s.r + (double)(Ar * dt) + (double)(Brr * z[0] * sdt);
     const double P1 = s.P + (double)(AP * dt);
