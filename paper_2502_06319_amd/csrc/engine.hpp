@@ -189,7 +189,7 @@ hipError_t launch_propagate_3d_mixed(const PropArgs<float>& a, int grid, int blo
 hipError_t launch_propagate_3d_fp64(const PropArgs<double>& a, int grid, int block, hipStream_t s);
 hipError_t launch_propagate_1d_mixed(const PropArgs<float>& a, int grid, int block, hipStream_t s);
 hipError_t launch_propagate_1d_fp64(const PropArgs<double>& a, int grid, int block, hipStream_t s);
-hipError_t occupancy_propagate(int model, int prec, int block, int shaped, int energy,
+hipError_t occupancy_propagate(int model, int prec, int block, int shaped, int energy, int ukey,
                                int* blocks_per_cu);
 hipError_t launch_reduce(const ReduceArgs& a, uint32_t n_segs, hipStream_t s);
 hipError_t launch_reweight(const ReweightArgs& a, uint32_t n_segs, hipStream_t s);

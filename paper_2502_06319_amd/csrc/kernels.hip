@@ -929,7 +929,7 @@ static void model3d_variants(int shaped, int energy, const void** f)
         keyed_variants<R, true, false, false>(f);
 }
 
-hipError_t occupancy_propagate(int model, int prec, int block, int shaped, int energy,
+hipError_t occupancy_propagate(int model, int prec, int block, int shaped, int energy, int ukey,
                                int* blocks_per_cu)
 {
     const void* f[2] = {nullptr, nullptr};
@@ -943,15 +943,12 @@ hipError_t occupancy_propagate(int model, int prec, int block, int shaped, int e
         keyed_variants<double, false, false, false>(f);
     else
         return hipErrorInvalidValue;
-    // the smaller residency of the two key variants, so either fits the grid
-    int lo = 1 << 30;
-    for (const void* fn : f) {
-        int n = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, block, 0);
-        if (e != hipSuccess) return e;
-        lo = n < lo ? n : lo;
-    }
-    *blocks_per_cu = lo;
+    // the variant the launch runs: one Philox key for the launch (f[1]) or a
+    // key per lane (f[0])
+    int n = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f[ukey ? 1 : 0], block, 0);
+    if (e != hipSuccess) return e;
+    *blocks_per_cu = n;
     return hipSuccess;
 }
 

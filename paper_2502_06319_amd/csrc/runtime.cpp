@@ -571,10 +571,11 @@ void make_chunks(const std::vector<SegmentDev>& segs, const std::vector<uint32_t
 }
 
 int grid_for(cosmica_ctx* ctx, int model, int prec, const cosmica_launch& L, uint64_t lanes_wanted,
-             bool shaped, bool energy)
+             bool shaped, bool energy, bool ukey)
 {
     int occ = 0;
-    if (occupancy_propagate(model, prec, L.block, shaped ? 1 : 0, energy ? 1 : 0, &occ) !=
+    if (occupancy_propagate(model, prec, L.block, shaped ? 1 : 0, energy ? 1 : 0, ukey ? 1 : 0,
+                            &occ) !=
             hipSuccess ||
         occ < 1)
         occ = 1;
@@ -753,7 +754,8 @@ cosmica_status execute_prop(cosmica_ctx* ctx, const PassDev& d)
         a.exL = d.exL;
         a.key_lo = (uint32_t)(d.key & 0xffffffffu);
         a.key_hi = (uint32_t)(d.key >> 32);
-        const int grid = grid_for(ctx, model, d.prec, L, d.model_particles[model], d.shaped, d.energy);
+        const int grid =
+            grid_for(ctx, model, d.prec, L, d.model_particles[model], d.shaped, d.energy, d.uniform_key);
         ctx->timings.grid_blocks = grid;
         ctx->timings.block = L.block;
         HIP_TRY(launch_model<R>(model, a, grid, L.block, ctx->stream));
@@ -1837,13 +1839,14 @@ cosmica_status sweep(cosmica_ctx* ctx, const cosmica_job* jobs, int n_jobs, int 
         if ((st = consider(cosmica_launch{blk, 0, best.chunk, best.order})) != COSMICA_OK) break;
     if (st == COSMICA_OK) {
         int occ = 0;
-        bool shaped_jobs = false, energy_jobs = false;
+        bool shaped_jobs = false, energy_jobs = false, one_key = true;
         for (int j = 0; j < n_jobs; ++j) {
             shaped_jobs |= job_shaped(copy_job(&jobs[j]));
             energy_jobs |= jobs[j].formulation == 1;
+            one_key &= jobs[j].seed == jobs[0].seed;
         }
         if (occupancy_propagate(model, precision, best.block, shaped_jobs ? 1 : 0,
-                                energy_jobs ? 1 : 0, &occ) != hipSuccess ||
+                                energy_jobs ? 1 : 0, one_key ? 1 : 0, &occ) != hipSuccess ||
             occ < 1)
             occ = 1;
         const cosmica_launch base = best;
@@ -2063,11 +2066,13 @@ cosmica_status group_create(cosmica_ctx* ctx, int model, int prec, ServeGroup** 
     if ((st = g->mem.alloc(&g->segs_d, (size_t)S * B)) != COSMICA_OK) return st;
     const cosmica_launch& L = ctx->launch[model][prec];
     g->block = L.block;
-    g->grid = grid_for(ctx, model, prec, L, ~0ull >> 8, false, false);
+    // serving launches run the per-lane-key variants (each request has its own seed)
+    g->grid = grid_for(ctx, model, prec, L, ~0ull >> 8, false, false, false);
     // slices with a squashed heliosphere or the energy form run the kernel
     // variants for them; the parking arrays are sized for the largest grid
     for (int v = 1; v < 4; ++v)
-        g->grid_var[v] = std::min(g->grid, grid_for(ctx, model, prec, L, ~0ull >> 8, v & 1, v & 2));
+        g->grid_var[v] =
+            std::min(g->grid, grid_for(ctx, model, prec, L, ~0ull >> 8, v & 1, v & 2, false));
     g->grid_var[0] = g->grid;
     g->susp_cap = (uint32_t)g->grid * (uint32_t)g->block;
     if ((st = g->mem.alloc(&g->susp[0], g->susp_cap)) != COSMICA_OK) return st;
