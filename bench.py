@@ -140,7 +140,10 @@ def serve(eng, seconds, rate, precision, seed=42, cut_at=None, poll_s=0.002):
     """Replay a Poisson stream of spectrum requests (the config-5 request mix);
     latency = arrival -> result on the host.  cut_at: cancel the requests still
     waiting for admission at that time (a saturated stream), so the leg ends
-    once the admitted ones finish; they are counted apart."""
+    once the admitted ones finish; they are counted apart.  A saturated leg also
+    reports its steady rate: the steps of the requests completed between a
+    quarter of the arrival window and the cut, over that time (the whole-leg
+    rate includes the ramp at the start and the drain after the cut)."""
     reqs = W.c5_requests(seed=seed, rate_hz=rate, duration_s=seconds)
     tickets = []
     lat = []
@@ -163,6 +166,7 @@ def serve(eng, seconds, rate, precision, seed=42, cut_at=None, poll_s=0.002):
     n_seen = 0
     cut = False
     last_done = t0
+    completions = []  # (seconds since t0, steps) per completed request
     while not (done.is_set() and finished + cancelled == len(tickets)):
         while n_seen < len(tickets):
             pending.append(tickets[n_seen])
@@ -189,7 +193,9 @@ def serve(eng, seconds, rate, precision, seed=42, cut_at=None, poll_s=0.002):
                     cancelled += 1
                 else:
                     lat.append(time.perf_counter() - t0 - arr)
-                    steps += int(tk.result()["steps"].sum())
+                    n = int(tk.result()["steps"].sum())
+                    steps += n
+                    completions.append((time.perf_counter() - t0, n))
                     finished += 1
                     last_done = time.perf_counter()
                 pending[i] = (arr, None)
@@ -208,6 +214,11 @@ def serve(eng, seconds, rate, precision, seed=42, cut_at=None, poll_s=0.002):
     }
     if cut_at is not None:
         out["cancelled_unadmitted"] = cancelled
+        w0, w1 = 0.25 * cut_at, cut_at
+        window = [n for t, n in completions if w0 <= t < w1]
+        out["steady_window_s"] = [round(w0, 1), round(w1, 1)]
+        out["steady_requests"] = len(window)
+        out["steady_steps_per_s"] = float(sum(window) / (w1 - w0))
     return out
 
 
@@ -494,6 +505,18 @@ def main():
         sat["frac_of_peak"] = round(sum(OPS_PER_STEP["3d"].values()) * sat["steps_per_s"]
                                     / 1e12 / PEAK_TOPS["mixed"], 4)
         sat["served_over_batched"] = round(sat["steps_per_s"] / value, 4)
+        sat["steady_over_batched"] = round(sat["steady_steps_per_s"] / value, 4)
+        # the same request mix as one batched pass (the stream's first 120
+        # requests): served over batched on work of one kind
+        same = [r["job"] for r in W.c5_requests(seed=44, rate_hz=2.0 * capacity,
+                                                 duration_s=args.saturate_seconds,
+                                                 max_requests=120)]
+        eng.run(same, "mixed")
+        t = eng.timings()
+        same_rate = t["steps"] / (t["propagate_ms"] * 1e-3)
+        sat["batched_same_requests"] = {"requests": len(same), "steps": int(t["steps"]),
+                                        "steps_per_s": same_rate}
+        sat["steady_over_same_batched"] = round(sat["steady_steps_per_s"] / same_rate, 4)
         serving["saturated_mixed"] = sat
         log("serving saturated:", sat)
     eng.close()

@@ -388,8 +388,9 @@ cosmica_status cosmica_cancel(cosmica_ctx* ctx, uint64_t ticket);
  * COSMICA_ENOTFOUND for an unknown ticket.  Thread-safe like cosmica_poll. */
 cosmica_status cosmica_request_state(cosmica_ctx* ctx, uint64_t ticket, int32_t* state);
 
-/* Serving counters: jobs queued, jobs resident, particles resident, device
- * bytes the context holds (live and kept for reuse). */
+/* Serving counters: jobs queued, jobs resident, particles parked between
+ * slices (as of the last slice the worker has read), device bytes the context
+ * holds (live and kept for reuse). */
 cosmica_status cosmica_serve_stats(cosmica_ctx* ctx, uint64_t* queued, uint64_t* resident,
                                    uint64_t* particles_in_flight, uint64_t* bytes_in_use);
 

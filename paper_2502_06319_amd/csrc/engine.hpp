@@ -87,11 +87,31 @@ struct alignas(16) LisDev {
     int32_t energy, pad0, pad1, pad2;
 };
 
-// Suspended particle (serving slices): full state, bit-exact on resume.
-struct alignas(16) SuspendDev {
-    double r, P, t, th, ph;
-    uint32_t n, seg, pid, pad0;
-    double T, lam;  // energy form
+// Parked particles of a serving slice, one array per field (lane i of a wave
+// writes entry base + i, so every store is contiguous): full state, bit-exact
+// on resume.  T and the loss integral belong to the energy form.
+struct ParkDev {
+    double *r, *P, *t, *th, *ph, *T, *lam;
+    uint32_t *n, *seg, *pid;
+};
+
+// The lists a serving slice works on, in device memory (one descriptor per
+// slice parity, written once): what the previous slice parked and left
+// unissued comes back first; this slice parks its own into the other lists.
+struct SliceDev {
+    ParkDev resume;
+    ParkDev suspend;
+    const uint32_t* n_resume;     // count of resume
+    uint32_t* resume_head;        // cursor over resume
+    uint32_t* suspend_count;
+    const ChunkDev* left_in;      // chunk remainders of the previous slice
+    const uint32_t* n_left_in;    // their count
+    uint32_t* left_in_head;       // cursor over left_in
+    ChunkDev* leftover;           // chunk remainders a wave holds when this slice ends
+    uint32_t* leftover_count;
+    uint32_t* overflow;           // set to 1 if suspend or leftover would overflow
+    uint32_t park_cap;            // entries of suspend
+    uint32_t left_cap;            // entries of leftover
 };
 
 template <typename R>
@@ -100,9 +120,11 @@ struct PropArgs {
     const RegionDev<R>* regions;  // jobs * kRegionStride
     const OrbitDev* orbit;        // orbit positions, indexed by JobDev::orbit_off
     const SegmentDev* segs;
+    // refill queue: positions [*head, q_tail) are still to be issued, position
+    // c at chunks[c & q_mask] (a ring buffer when q_mask + 1 is its size)
     const ChunkDev* chunks;
-    uint32_t n_chunks;
-    uint32_t* head;               // chunk cursor, zeroed before launch
+    unsigned long long* head;
+    uint64_t q_tail, q_mask;
     // exit records, indexed by segment out_offset + particle
     double* exP;
     double* exT;
@@ -111,12 +133,7 @@ struct PropArgs {
     double* exR;   // optional (nullptr)
     double* exTh;
     double* exPh;
-    // serving slices: resume list in, suspend list out
-    const SuspendDev* resume;
-    uint32_t n_resume;
-    uint32_t* resume_head;        // cursor over the resume list, zeroed before launch
-    SuspendDev* suspend;
-    uint32_t* suspend_count;      // zeroed before launch
+    const SliceDev* slice;        // serving slices (nullptr: one whole pass)
     uint32_t step_budget;         // steps per wave per launch (0xffffffff: unlimited)
     uint64_t slice_ticks;         // launch length in device wall-clock ticks (0: unlimited)
     uint32_t uniform_key;         // 1: every job of the launch has the Philox key below
@@ -125,8 +142,20 @@ struct PropArgs {
     uint32_t key_lo, key_hi;
     const uint32_t* job_cancel;   // optional per-job cancel flags
     uint32_t* job_done;           // optional per-job count of finished particles
-    ChunkDev* leftover;           // chunk remainders a wave held when its slice ended
-    uint32_t* leftover_count;     // zeroed before launch
+};
+
+// End of a serving slice (one workgroup, after the propagation kernel):
+// resume entries and chunk remainders of the previous slice that no wave
+// claimed move to this slice's lists (those of cancelled jobs are dropped),
+// the queue head is clamped to the slice's tail (waves that found the queue
+// empty advanced it past), and the next slice's counters are cleared.
+struct CloseArgs {
+    SliceDev sl;  // the slice's lists: resume / left_in in, suspend / leftover out
+    unsigned long long* head;
+    uint64_t q_tail;
+    const SegmentDev* segs;
+    const uint32_t* job_cancel;
+    uint32_t* next_counters;  // 4 words cleared at the end
 };
 
 struct ReduceArgs {
@@ -195,6 +224,7 @@ hipError_t launch_reduce(const ReduceArgs& a, uint32_t n_segs, hipStream_t s);
 hipError_t launch_reweight(const ReweightArgs& a, uint32_t n_segs, hipStream_t s);
 hipError_t launch_exit_range(const RangeArgs& a, uint32_t n_segs, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint32_t n, hipStream_t s);
+hipError_t launch_slice_close(const CloseArgs& a, hipStream_t s);
 // Exit records [0, n) from the per-field arrays (L, R, Th, Ph may be null: 0).
 hipError_t launch_pack_exits(const double* P, const double* T, const uint32_t* NF,
                              const double* L, const double* R, const double* Th,

@@ -632,13 +632,18 @@ k_propagate(const PropArgs<R> a)
     // every wave reads from the device's constant-rate clock, so the waves stop
     // together instead of the slice waiting for its slowest wave's budget
     uint32_t wave_steps = 0;
-    const bool sliced = a.step_budget != 0xffffffffu || a.slice_ticks != 0;
+    // a serving slice parks into the lists of its descriptor
+    const SliceDev* sv = a.slice;
+    const bool sliced = sv != nullptr && (a.step_budget != 0xffffffffu || a.slice_ticks != 0);
     const uint64_t t_stop =
         a.slice_ticks != 0 ? (uint64_t)wall_clock64() + a.slice_ticks : ~(uint64_t)0;
 
     // wave-uniform refill cursors
     uint32_t c_seg = 0, c_next = 0, c_end = 0;
-    bool resume_open = a.n_resume > 0;
+    // the counts of a slice's resume and remainder lists are read where they are
+    // used (kept live across the kernel they would cost registers)
+    bool resume_open = sv != nullptr;
+    bool left_open = sv != nullptr;
     bool queue_open = true;
     bool launch_open = true;  // false once this wave used its step budget
 
@@ -648,25 +653,28 @@ k_propagate(const PropArgs<R> a)
         while (need != 0 && resume_open && launch_open) {
             uint32_t base = 0;
             const uint32_t cnt = (uint32_t)__popcll(need);
-            if (lane == 0) base = atomicAdd(a.resume_head, cnt);
+            if (lane == 0) base = atomicAdd(sv->resume_head, cnt);
             base = wave_uniform(base);
-            if (base >= a.n_resume) {
+            // (a count past the list's capacity only follows an overflow,
+            // which the host reports as an error)
+            const uint32_t n_resume = min(*sv->n_resume, sv->park_cap);
+            if (base >= n_resume) {
                 resume_open = false;
                 break;
             }
             const uint32_t rank = lane_rank(need);
-            if (!active && base + rank < a.n_resume) {
-                // field by field, so kernels without the energy form leave T
-                // and the loss unread
-                const SuspendDev* q = a.resume + base + rank;
-                s.r = q->r;
-                s.P = q->P;
-                s.t = q->t;
-                s.th = (R)q->th;
-                s.ph = (R)q->ph;
-                s.n = q->n;
-                seg = q->seg;
-                pid = q->pid;
+            if (!active && base + rank < n_resume) {
+                // kernels without the energy form leave T and the loss unread
+                const uint32_t i = base + rank;
+                const ParkDev& q = sv->resume;
+                s.r = q.r[i];
+                s.P = q.P[i];
+                s.t = q.t[i];
+                s.th = (R)q.th[i];
+                s.ph = (R)q.ph[i];
+                s.n = q.n[i];
+                seg = q.seg[i];
+                pid = q.pid[i];
                 const SegmentDev sg = a.segs[seg];
                 job = sg.job;
                 bin = sg.bin;
@@ -675,8 +683,8 @@ k_propagate(const PropArgs<R> a)
                 if (ENERGY) {
                     // momentum-form particles may have been parked by a kernel
                     // that did not store T and the loss
-                    s.T = J.energy ? q->T : 0.0;
-                    s.lam = J.energy ? q->lam : 0.0;
+                    s.T = J.energy ? q.T[i] : 0.0;
+                    s.lam = J.energy ? q.lam[i] : 0.0;
                 }
                 jd = a.jobs + job;
                 reg.off = job * (uint32_t)(kRegionStride * sizeof(RegionDev<R>));
@@ -687,14 +695,31 @@ k_propagate(const PropArgs<R> a)
         // 2) new particles from the chunk queue
         while (need != 0 && !resume_open && queue_open && launch_open) {
             if (c_next == c_end) {
-                uint32_t c = 0;
-                if (lane == 0) c = atomicAdd(a.head, 1u);
-                c = wave_uniform(c);
-                if (c >= a.n_chunks) {
-                    queue_open = false;
-                    break;
+                // remainders the previous slice left unissued go first
+                ChunkDev ch;
+                bool got = false;
+                if (left_open) {
+                    uint32_t c = 0;
+                    if (lane == 0) c = atomicAdd(sv->left_in_head, 1u);
+                    c = wave_uniform(c);
+                    if (c < min(*sv->n_left_in, sv->left_cap)) {
+                        ch = sv->left_in[c];
+                        got = true;
+                    } else {
+                        left_open = false;
+                    }
                 }
-                const ChunkDev ch = a.chunks[c];
+                if (!got) {
+                    unsigned long long c = 0;
+                    if (lane == 0) c = atomicAdd(a.head, 1ull);
+                    c = ((unsigned long long)wave_uniform((uint32_t)(c >> 32)) << 32) |
+                        wave_uniform((uint32_t)c);
+                    if (c >= a.q_tail) {
+                        queue_open = false;
+                        break;
+                    }
+                    ch = a.chunks[c & a.q_mask];
+                }
                 c_seg = wave_uniform(ch.seg);
                 c_next = wave_uniform(ch.first);
                 c_end = c_next + wave_uniform(ch.count);
@@ -739,15 +764,21 @@ k_propagate(const PropArgs<R> a)
             need = __ballot(!active);
         }
         if (!__any(active)) {
-            // hand back the unissued rest of this wave's chunk
-            if (c_next < c_end && lane == 0 && a.leftover != nullptr) {
-                const uint32_t slot = atomicAdd(a.leftover_count, 1u);
-                ChunkDev ch;
-                ch.seg = c_seg;
-                ch.first = c_next;
-                ch.count = c_end - c_next;
-                ch.pad0 = 0;
-                a.leftover[slot] = ch;
+            // hand back the unissued rest of this wave's chunk (nothing of a
+            // cancelled job)
+            if (c_next < c_end && lane == 0 && sv != nullptr &&
+                !(a.job_cancel != nullptr && a.job_cancel[a.segs[c_seg].job] != 0u)) {
+                const uint32_t slot = atomicAdd(sv->leftover_count, 1u);
+                if (slot < sv->left_cap) {
+                    ChunkDev ch;
+                    ch.seg = c_seg;
+                    ch.first = c_next;
+                    ch.count = c_end - c_next;
+                    ch.pad0 = 0;
+                    sv->leftover[slot] = ch;
+                } else {
+                    *sv->overflow = 1u;
+                }
             }
             break;
         }
@@ -833,25 +864,33 @@ k_propagate(const PropArgs<R> a)
             active = false;
         }
         if (slice_over) {
-            // slice over: park the wave's particles for the next launch and stop
-            // taking work
-            if (active) {
-                const uint32_t slot = atomicAdd(a.suspend_count, 1u);
-                // an energy-form particle is only ever parked by a launch of the
-                // energy-form kernel, so only that kernel stores T and the loss
-                SuspendDev* q = a.suspend + slot;
-                q->r = s.r;
-                q->P = s.P;
-                q->t = s.t;
-                q->th = (double)s.th;
-                q->ph = (double)s.ph;
-                q->n = s.n;
-                q->seg = seg;
-                q->pid = pid;
-                q->pad0 = 0;
-                if (ENERGY) {
-                    q->T = s.T;
-                    q->lam = s.lam;
+            // slice over (wave-uniform): park the wave's particles in
+            // consecutive entries for the next launch and stop taking work
+            const uint64_t parked = __ballot(active);
+            if (parked != 0) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(sv->suspend_count, (uint32_t)__popcll(parked));
+                base = wave_uniform(base);
+                const uint32_t i = base + lane_rank(parked);
+                const ParkDev& q = sv->suspend;
+                if (active && i < sv->park_cap) {
+                    q.r[i] = s.r;
+                    q.P[i] = s.P;
+                    q.t[i] = s.t;
+                    q.th[i] = (double)s.th;
+                    q.ph[i] = (double)s.ph;
+                    q.n[i] = s.n;
+                    q.seg[i] = seg;
+                    q.pid[i] = pid;
+                    // an energy-form particle is only ever parked by a launch of
+                    // the energy-form kernel, so only that kernel stores T and
+                    // the loss
+                    if (ENERGY) {
+                        q.T[i] = s.T;
+                        q.lam[i] = s.lam;
+                    }
+                } else if (active) {
+                    *sv->overflow = 1u;
                 }
                 active = false;
             }
@@ -956,8 +995,11 @@ hipError_t occupancy_propagate(int model, int prec, int block, int shaped, int e
 // Per-bin reduction.
 // ---------------------------------------------------------------------------
 constexpr int kReduceBlock = 256;
+// The reduction of one rigidity bin runs in one workgroup; a served request
+// reduces its few bins alone, so each one takes a whole CU's worth of waves.
+constexpr int kBinBlock = 1024;
 
-template <typename T>
+template <typename T, int B = kReduceBlock>
 __device__ __forceinline__ T block_sum(T v, T* sh)
 {
     // fixed-order tree: wave shuffles, then the wave partials in LDS
@@ -968,7 +1010,7 @@ __device__ __forceinline__ T block_sum(T v, T* sh)
     __syncthreads();
     T t = 0;
     if (threadIdx.x == 0) {
-        for (int i = 0; i < kReduceBlock / 64; ++i) t += sh[i];
+        for (int i = 0; i < B / 64; ++i) t += sh[i];
         sh[0] = t;
     }
     __syncthreads();
@@ -997,21 +1039,21 @@ __device__ __forceinline__ double energy_weight(const LisDev& L, double beta0, d
     return beta0 / beta_of(L, P) * (L.norm * ::pow(P, -L.index)) * ::exp(-loss);
 }
 
-__global__ void __launch_bounds__(kReduceBlock) k_reduce(const ReduceArgs a)
+__global__ void __launch_bounds__(kBinBlock) k_reduce(const ReduceArgs a)
 {
     __shared__ uint32_t hist[kNHist];
-    __shared__ double shd[kReduceBlock / 64];
-    __shared__ unsigned long long shu[kReduceBlock / 64];
+    __shared__ double shd[kBinBlock / 64];
+    __shared__ unsigned long long shu[kBinBlock / 64];
     const uint32_t sidx = a.seg_base + blockIdx.x;
     const SegmentDev sg = a.segs[sidx];
     const LisDev L = a.lis[sg.job];
-    for (int i = threadIdx.x; i < kNHist; i += kReduceBlock) hist[i] = 0u;
+    for (int i = threadIdx.x; i < kNHist; i += kBinBlock) hist[i] = 0u;
     __syncthreads();
     double sw = 0.0, st = 0.0;
     unsigned long long sn = 0, ncap = 0, nnan = 0, nused = 0;
     const double inv_p0 = 1.0 / sg.P0;
     const double beta0 = L.energy ? beta_of(L, sg.P0) : 0.0;
-    for (uint32_t i = threadIdx.x; i < sg.count; i += kReduceBlock) {
+    for (uint32_t i = threadIdx.x; i < sg.count; i += kBinBlock) {
         const uint32_t o = sg.out_offset + i;
         const uint32_t nf = a.exNF[o];
         const uint32_t fl = nf >> kFlagShift;
@@ -1032,17 +1074,17 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(const ReduceArgs a)
         j = j < 0 ? 0 : (j > 128 ? 128 : j);
         atomicAdd(&hist[j], 1u);
     }
-    const double SW = block_sum<double>(sw, shd);
-    const double ST = block_sum<double>(st, shd);
-    const unsigned long long SN = block_sum<unsigned long long>(sn, shu);
-    const unsigned long long NC = block_sum<unsigned long long>(ncap, shu);
-    const unsigned long long NN = block_sum<unsigned long long>(nnan, shu);
-    const unsigned long long NU = block_sum<unsigned long long>(nused, shu);
+    const double SW = block_sum<double, kBinBlock>(sw, shd);
+    const double ST = block_sum<double, kBinBlock>(st, shd);
+    const unsigned long long SN = block_sum<unsigned long long, kBinBlock>(sn, shu);
+    const unsigned long long NC = block_sum<unsigned long long, kBinBlock>(ncap, shu);
+    const unsigned long long NN = block_sum<unsigned long long, kBinBlock>(nnan, shu);
+    const unsigned long long NU = block_sum<unsigned long long, kBinBlock>(nused, shu);
     const double N = (double)NU;
     const double mean = NU > 0 ? SW / N : 0.0;
     double ss = 0.0;
     if (NU > 1) {
-        for (uint32_t i = threadIdx.x; i < sg.count; i += kReduceBlock) {
+        for (uint32_t i = threadIdx.x; i < sg.count; i += kBinBlock) {
             const uint32_t o = sg.out_offset + i;
             if ((a.exNF[o] >> kFlagShift) != 0u) continue;
             const double w = L.energy ? energy_weight(L, beta0, a.exP[o], a.exL[o])
@@ -1051,11 +1093,11 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(const ReduceArgs a)
             ss += dw * dw;
         }
     }
-    const double SS = block_sum<double>(ss, shd);
+    const double SS = block_sum<double, kBinBlock>(ss, shd);
     __syncthreads();
     const uint32_t ob = a.out_base + blockIdx.x;
     if (a.hist != nullptr)
-        for (int i = threadIdx.x; i < kNHist; i += kReduceBlock)
+        for (int i = threadIdx.x; i < kNHist; i += kBinBlock)
             a.hist[(size_t)ob * kNHist + i] = hist[i];
     if (threadIdx.x == 0) {
         // momentum form: mean of f_LIS(P_ex) times P0^2; energy form: the mean
@@ -1073,7 +1115,7 @@ __global__ void __launch_bounds__(kReduceBlock) k_reduce(const ReduceArgs a)
 hipError_t launch_reduce(const ReduceArgs& a, uint32_t n_segs, hipStream_t s)
 {
     if (n_segs == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce, dim3(n_segs), dim3(kReduceBlock), 0, s, a);
+    hipLaunchKernelGGL(k_reduce, dim3(n_segs), dim3(kBinBlock), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1252,6 +1294,60 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, uint32_t n, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+// One workgroup: the leftovers of a slice are few (none unless the slice ran a
+// kernel variant with fewer lanes than the previous one).
+__global__ void __launch_bounds__(256) k_slice_close(const CloseArgs a)
+{
+    const SliceDev& sl = a.sl;
+    const uint32_t n_in = min(*sl.n_resume, sl.park_cap);
+    const uint32_t in_head = *sl.resume_head;
+    const uint32_t n_lin = min(*sl.n_left_in, sl.left_cap);
+    const uint32_t lin_head = *sl.left_in_head;
+    for (uint32_t i = (in_head < n_in ? in_head : n_in) + threadIdx.x; i < n_in; i += blockDim.x) {
+        const uint32_t seg = sl.resume.seg[i];
+        if (a.job_cancel != nullptr && a.job_cancel[a.segs[seg].job] != 0u) continue;
+        const uint32_t o = atomicAdd(sl.suspend_count, 1u);
+        if (o >= sl.park_cap) {
+            *sl.overflow = 1u;
+            continue;
+        }
+        const ParkDev& in = sl.resume;
+        const ParkDev& out = sl.suspend;
+        out.r[o] = in.r[i];
+        out.P[o] = in.P[i];
+        out.t[o] = in.t[i];
+        out.th[o] = in.th[i];
+        out.ph[o] = in.ph[i];
+        out.T[o] = in.T[i];
+        out.lam[o] = in.lam[i];
+        out.n[o] = in.n[i];
+        out.seg[o] = seg;
+        out.pid[o] = in.pid[i];
+    }
+    for (uint32_t i = (lin_head < n_lin ? lin_head : n_lin) + threadIdx.x; i < n_lin;
+         i += blockDim.x) {
+        const ChunkDev ch = sl.left_in[i];
+        if (a.job_cancel != nullptr && a.job_cancel[a.segs[ch.seg].job] != 0u) continue;
+        const uint32_t o = atomicAdd(sl.leftover_count, 1u);
+        if (o >= sl.left_cap) {
+            *sl.overflow = 1u;
+            continue;
+        }
+        sl.leftover[o] = ch;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (*a.head > a.q_tail) *a.head = a.q_tail;
+        for (int k = 0; k < 4; ++k) a.next_counters[k] = 0u;
+    }
+}
+
+hipError_t launch_slice_close(const CloseArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_slice_close, dim3(1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

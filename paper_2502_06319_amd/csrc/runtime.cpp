@@ -332,6 +332,7 @@ struct Pool;
 
 struct Req;
 struct ServeGroup;
+struct ServeHost;
 
 // The device array behind cosmica_run_static: file scope, so each GPU the
 // library runs on holds one copy from module load until the process ends.
@@ -418,6 +419,7 @@ struct cosmica_ctx {
     std::map<uint64_t, std::unique_ptr<Req>> reqs;
     std::unique_ptr<ServeGroup> groups[2][2];
     hipStream_t serve_stream = nullptr;
+    std::unique_ptr<ServeHost> serve_host;  // the worker's pinned buffers and events
     cosmica_status serve_error = COSMICA_OK;
     std::unique_ptr<StaticHost> stat;  // host staging of cosmica_run_static
     cosmica_ctx() = default;
@@ -632,7 +634,7 @@ struct cosmica_plan {
     OrbitDev* orbit_d = nullptr;
     SegmentDev* segs_d = nullptr;
     ChunkDev* chunks_d[2] = {nullptr, nullptr};
-    uint32_t* counters_d = nullptr;  // [head0, head1, resume_head, suspend_count, leftover_count]
+    uint32_t* counters_d = nullptr;  // 8 words: the queue heads of the two models (64-bit each)
     double* exP = nullptr;
     double* exT = nullptr;
     uint32_t* exNF = nullptr;
@@ -707,7 +709,7 @@ struct PassDev {
     const ChunkDev* chunks[2];  // the refill queues of the radial and 3D groups
     uint32_t n_chunks[2];
     uint64_t model_particles[2];
-    uint32_t* counters;  // [head0, head1, resume_head, suspend_count, leftover_count]
+    uint32_t* counters;  // 8 words, zeroed: the queue heads of the two models (64-bit each)
     double *exP, *exT, *exL, *exR, *exTh, *exPh;
     uint32_t* exNF;
     bool uniform_key, shaped, energy;
@@ -729,25 +731,21 @@ cosmica_status execute_prop(cosmica_ctx* ctx, const PassDev& d)
         a.orbit = d.orbit;
         a.segs = d.segs;
         a.chunks = d.chunks[model];
-        a.n_chunks = nch;
-        a.head = d.counters + model;
+        a.head = (unsigned long long*)(d.counters + 2 * model);
+        a.q_tail = nch;
+        a.q_mask = ~0ull;
         a.exP = d.exP;
         a.exT = d.exT;
         a.exNF = d.exNF;
         a.exR = d.exR;
         a.exTh = d.exTh;
         a.exPh = d.exPh;
-        a.resume = nullptr;
-        a.n_resume = 0;
-        a.resume_head = d.counters + 2;
-        a.suspend = nullptr;
-        a.suspend_count = d.counters + 3;
+        // one whole pass: nothing parked, nothing left over (the serving fields
+        // stay null)
         a.step_budget = 0xffffffffu;
         a.slice_ticks = 0;
         a.job_cancel = nullptr;
         a.job_done = nullptr;
-        a.leftover = nullptr;
-        a.leftover_count = d.counters + 4;
         a.uniform_key = d.uniform_key ? 1u : 0u;
         a.shaped = d.shaped ? 1u : 0u;
         a.energy = d.energy ? 1u : 0u;
@@ -1934,7 +1932,9 @@ extern "C" cosmica_status cosmica_tune_jobs(cosmica_ctx* ctx, const cosmica_job*
 // Requests are admitted while their exit records fit in the device pool; the
 // particles of every admitted request share the same launches, and particles
 // still inside at the end of a slice are parked (bit-exact) and resumed first
-// in the next one.
+// in the next one.  The work queue, the parked particles and every cursor over
+// them stay on the device, so the worker enqueues a group's next slice before
+// it reads what the previous one did, and the device runs slices back to back.
 // ---------------------------------------------------------------------------
 struct Req {
     uint64_t ticket = 0;
@@ -1948,12 +1948,50 @@ struct Req {
     bool cancel_sent = false;
     int slot = -1;
     uint64_t ex0 = 0;
-    uint64_t ring_end = 0;  // queue position just past the request's last chunk
+    uint64_t ring_end = 0;      // queue position just past the request's last chunk
+    uint64_t first_slice = 0;   // first slice of its group that can hold its particles
+    uint64_t cancel_slice = 0;  // first slice of its group that sees its cancel flag
+    // reduced results on their way to the host, and the event that ends the copy
+    unsigned char* staged = nullptr;
+    hipEvent_t staged_ev = nullptr;
+};
+
+// Pinned host memory and events of the serving worker.
+struct ServeHost {
+    // Uploads go through two pinned arenas used by alternate rounds of the
+    // worker.  The uploads of round i are enqueued before round i's slices,
+    // and round i+1 waits for those slices, so round i+2 finds arena i % 2 free.
+    static constexpr size_t kArenaBytes = 16u << 20;
+    unsigned char* arena[2] = {nullptr, nullptr};
+    int cur = 0;
+    size_t used = 0;
+    // per finished request: its reduced bins (at most kBinsPerSlot of them)
+    static constexpr size_t kResultBytes = 40960;
+    std::vector<unsigned char*> blocks, free_blocks;
+    std::vector<hipEvent_t> events, free_events;
+    hipEvent_t round_ev[2] = {nullptr, nullptr};
+    std::vector<Req*> finishing;  // results being copied to the host
+    ~ServeHost()
+    {
+        for (unsigned char* a : arena)
+            if (a) (void)hipHostFree(a);
+        for (unsigned char* b : blocks) (void)hipHostFree(b);
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (hipEvent_t e : round_ev)
+            if (e) (void)hipEventDestroy(e);
+    }
 };
 
 struct ServeGroup {
     static constexpr uint32_t kSlots = 256;
     static constexpr uint32_t kBinsPerSlot = 64;
+    // Control words on the device: the queue head (64-bit), per slice parity p
+    // the words at kCtlPark + 4 p: [particles parked, chunk remainders, resume
+    // cursor, remainder cursor]; an overflow flag; finished particles per slot.
+    // A slice of parity p resumes the lists of parity 1 - p and writes those of
+    // parity p; its closing kernel clears the counters of parity 1 - p.
+    static constexpr uint32_t kCtlPark = 4, kCtlOverflow = 12, kCtlDone = 16;
+    static constexpr uint32_t kCtlWords = kCtlDone + kSlots;
     int model = 0, prec = 0;
     cosmica_ctx* ctx = nullptr;
     DevSet mem;
@@ -1962,28 +2000,29 @@ struct ServeGroup {
     LisDev* lis_d = nullptr;
     OrbitDev* orbit_d = nullptr;  // kSlots * COSMICA_MAX_ORBIT positions
     uint32_t* cancel_d = nullptr;
-    uint32_t* done_d = nullptr;
     SegmentDev* segs_d = nullptr;
-    // Work queue of the admitted requests' chunks, resident on the device:
-    // entries [q_head, q_tail) of ring_d are still to be issued.  A request's
-    // chunks are uploaded once, when it is admitted; a slice issues from q_head
-    // on, and chunks a wave held unfinished when the slice ended go back in
-    // front of q_head.
+    uint32_t* ctl_d = nullptr;
+    uint32_t* snap_h = nullptr;  // pinned: the control words after each slice, by parity
+    // Work queue of the admitted requests' chunks: a ring of ring_cap (a power
+    // of two) entries on the device, position c at c & (ring_cap - 1).  The host
+    // appends at q_tail; the device advances the head.  q_head is the head as
+    // of the last slice the worker has read (a lower bound of the device's).
     ChunkDev* ring_d = nullptr;
     uint64_t ring_cap = 0;
     uint64_t q_head = 0, q_tail = 0;
+    uint64_t seq = 0;            // slices enqueued
+    uint64_t in_flight = 0;      // particles parked after the last slice read
     uint64_t pool_cap = 0;
     double* exL = nullptr;  // energy form: allocated when the first energy-form request arrives
     double* exP = nullptr;
     double* exT = nullptr;
     uint32_t* exNF = nullptr;
-    SuspendDev* susp[2] = {nullptr, nullptr};
-    uint32_t susp_cap = 0;
-    int cur = 0;
-    uint32_t n_resume = 0;
-    ChunkDev* left_d = nullptr;
+    ParkDev park[2] = {};
+    uint32_t park_cap = 0;
+    ChunkDev* left_d[2] = {nullptr, nullptr};
     uint32_t left_cap = 0;
-    uint32_t* counters_d = nullptr;  // head, resume_head, suspend_count, leftover_count
+    SliceDev slice_h[2] = {};    // the lists of a slice of each parity
+    SliceDev* slice_d = nullptr;  // the same on the device
     uint32_t* r_hist = nullptr;
     double* r_flux = nullptr;
     double* r_se = nullptr;
@@ -1994,13 +2033,16 @@ struct ServeGroup {
     std::vector<int> free_slots;
     std::vector<SegmentDev> segs_h;
     std::map<uint64_t, uint64_t> free_ranges;  // offset -> length of free pool ranges
-    std::vector<uint8_t> slot_cancelled;       // per slot: its request was cancelled
     std::vector<Req*> resident;
-    std::vector<Req*> releasing;               // cancelled, freed once none of their work is queued
+    std::vector<Req*> releasing;               // cancelled, freed once none of their work is left
     int grid = 0, block = 256;
     int grid_var[4] = {0, 0, 0, 0};  // by (shaped | 2 energy)
-    uint32_t n_chunks_last = 0;
     explicit ServeGroup(cosmica_ctx* c) : ctx(c), mem(c) {}
+    ~ServeGroup()
+    {
+        if (snap_h) (void)hipHostFree(snap_h);
+    }
+    static uint32_t park_word(int parity, int k) { return kCtlPark + 4u * (uint32_t)parity + (uint32_t)k; }
 };
 
 cosmica_ctx::~cosmica_ctx() = default;
@@ -2036,6 +2078,42 @@ uint64_t pool_particles(cosmica_ctx* ctx)
     return std::min<uint64_t>(want, room / 20);
 }
 
+cosmica_status serve_host_init(cosmica_ctx* ctx)
+{
+    auto H = std::make_unique<ServeHost>();
+    for (int i = 0; i < 2; ++i) {
+        HIP_TRY(hipHostMalloc((void**)&H->arena[i], ServeHost::kArenaBytes, hipHostMallocDefault));
+        HIP_TRY(hipEventCreateWithFlags(&H->round_ev[i], hipEventDisableTiming));
+    }
+    ctx->serve_host = std::move(H);
+    return COSMICA_OK;
+}
+
+// Copies host bytes to the device on the serving stream, staged in the
+// current round's pinned arena (the source may go away at once).
+cosmica_status upload(cosmica_ctx* ctx, void* dst, const void* src, size_t bytes)
+{
+    if (bytes == 0) return COSMICA_OK;
+    ServeHost& H = *ctx->serve_host;
+    hipStream_t s = ctx->serve_stream;
+    if (bytes > ServeHost::kArenaBytes) {
+        HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));  // pageable source
+        return COSMICA_OK;
+    }
+    size_t off = (H.used + 255) & ~(size_t)255;
+    if (off + bytes > ServeHost::kArenaBytes) {
+        // every copy enqueued so far is done: both arenas are free
+        HIP_TRY(hipStreamSynchronize(s));
+        off = 0;
+    }
+    unsigned char* p = H.arena[H.cur] + off;
+    std::memcpy(p, src, bytes);
+    H.used = off + bytes;
+    HIP_TRY(hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, s));
+    return COSMICA_OK;
+}
+
 template <typename R>
 cosmica_status group_alloc_tables(ServeGroup* g)
 {
@@ -2047,6 +2125,27 @@ cosmica_status group_alloc_tables(ServeGroup* g)
         return st;
     g->jobs_d = jd;
     g->regions_d = rd;
+    return COSMICA_OK;
+}
+
+cosmica_status park_alloc(ServeGroup* g, ParkDev* pk)
+{
+    const size_t n = g->park_cap;
+    unsigned char* b = nullptr;
+    cosmica_status st = g->mem.alloc(&b, n * (7 * sizeof(double) + 3 * sizeof(uint32_t)));
+    if (st != COSMICA_OK) return st;
+    double* d = (double*)b;
+    pk->r = d;
+    pk->P = d + n;
+    pk->t = d + 2 * n;
+    pk->th = d + 3 * n;
+    pk->ph = d + 4 * n;
+    pk->T = d + 5 * n;
+    pk->lam = d + 6 * n;
+    uint32_t* u = (uint32_t*)(d + 7 * n);
+    pk->n = u;
+    pk->seg = u + n;
+    pk->pid = u + 2 * n;
     return COSMICA_OK;
 }
 
@@ -2062,24 +2161,46 @@ cosmica_status group_create(cosmica_ctx* ctx, int model, int prec, ServeGroup** 
     if ((st = g->mem.alloc(&g->lis_d, S)) != COSMICA_OK) return st;
     if ((st = g->mem.alloc(&g->orbit_d, (size_t)S * COSMICA_MAX_ORBIT)) != COSMICA_OK) return st;
     if ((st = g->mem.alloc(&g->cancel_d, S)) != COSMICA_OK) return st;
-    if ((st = g->mem.alloc(&g->done_d, S)) != COSMICA_OK) return st;
     if ((st = g->mem.alloc(&g->segs_d, (size_t)S * B)) != COSMICA_OK) return st;
+    if ((st = g->mem.alloc(&g->ctl_d, ServeGroup::kCtlWords)) != COSMICA_OK) return st;
+    HIP_TRY(hipHostMalloc((void**)&g->snap_h, 2 * ServeGroup::kCtlWords * sizeof(uint32_t),
+                          hipHostMallocDefault));
     const cosmica_launch& L = ctx->launch[model][prec];
     g->block = L.block;
     // serving launches run the per-lane-key variants (each request has its own seed)
     g->grid = grid_for(ctx, model, prec, L, ~0ull >> 8, false, false, false);
     // slices with a squashed heliosphere or the energy form run the kernel
-    // variants for them; the parking arrays are sized for the largest grid
+    // variants for them; the parking lists are sized for the largest grid
     for (int v = 1; v < 4; ++v)
         g->grid_var[v] =
             std::min(g->grid, grid_for(ctx, model, prec, L, ~0ull >> 8, v & 1, v & 2, false));
     g->grid_var[0] = g->grid;
-    g->susp_cap = (uint32_t)g->grid * (uint32_t)g->block;
-    if ((st = g->mem.alloc(&g->susp[0], g->susp_cap)) != COSMICA_OK) return st;
-    if ((st = g->mem.alloc(&g->susp[1], g->susp_cap)) != COSMICA_OK) return st;
-    g->left_cap = g->susp_cap / 64 + 64;
-    if ((st = g->mem.alloc(&g->left_d, g->left_cap)) != COSMICA_OK) return st;
-    if ((st = g->mem.alloc(&g->counters_d, 8)) != COSMICA_OK) return st;
+    g->park_cap = (uint32_t)g->grid * (uint32_t)g->block;
+    for (int p = 0; p < 2; ++p)
+        if ((st = park_alloc(g.get(), &g->park[p])) != COSMICA_OK) return st;
+    g->left_cap = g->park_cap / 64 + 64;  // one remainder per wave
+    for (int p = 0; p < 2; ++p)
+        if ((st = g->mem.alloc(&g->left_d[p], g->left_cap)) != COSMICA_OK) return st;
+    for (int p = 0; p < 2; ++p) {
+        const int o = p ^ 1;
+        SliceDev& v = g->slice_h[p];
+        uint32_t* c = g->ctl_d;
+        v.resume = g->park[o];
+        v.suspend = g->park[p];
+        v.n_resume = c + ServeGroup::park_word(o, 0);
+        v.resume_head = c + ServeGroup::park_word(p, 2);
+        v.suspend_count = c + ServeGroup::park_word(p, 0);
+        v.left_in = g->left_d[o];
+        v.n_left_in = c + ServeGroup::park_word(o, 1);
+        v.left_in_head = c + ServeGroup::park_word(p, 3);
+        v.leftover = g->left_d[p];
+        v.leftover_count = c + ServeGroup::park_word(p, 1);
+        v.overflow = c + ServeGroup::kCtlOverflow;
+        v.park_cap = g->park_cap;
+        v.left_cap = g->left_cap;
+    }
+    if ((st = g->mem.alloc(&g->slice_d, 2)) != COSMICA_OK) return st;
+    HIP_TRY(hipMemcpy(g->slice_d, g->slice_h, sizeof(g->slice_h), hipMemcpyHostToDevice));
     if ((st = g->mem.alloc(&g->r_hist, (size_t)B * kNHist)) != COSMICA_OK) return st;
     if ((st = g->mem.alloc(&g->r_flux, B)) != COSMICA_OK) return st;
     if ((st = g->mem.alloc(&g->r_se, B)) != COSMICA_OK) return st;
@@ -2095,12 +2216,11 @@ cosmica_status group_create(cosmica_ctx* ctx, int model, int prec, ServeGroup** 
     g->ring_cap = 1u << 20;
     if ((st = dalloc(ctx, g->ring_cap * sizeof(ChunkDev), (void**)&g->ring_d)) != COSMICA_OK)
         return st;
-    g->slot_cancelled.assign(S, 0);
     g->free_ranges[0] = g->pool_cap;
     for (int s = (int)S - 1; s >= 0; --s) g->free_slots.push_back(s);
     g->segs_h.resize((size_t)S * B);
     HIP_TRY(launch_fill_u32(g->cancel_d, 0u, S, ctx->serve_stream));
-    HIP_TRY(launch_fill_u32(g->done_d, 0u, S, ctx->serve_stream));
+    HIP_TRY(launch_fill_u32(g->ctl_d, 0u, ServeGroup::kCtlWords, ctx->serve_stream));
     *out = g.release();
     return COSMICA_OK;
 }
@@ -2136,50 +2256,49 @@ void pool_give(ServeGroup* g, uint64_t off, uint64_t n)
     }
 }
 
-// Appends chunks at the queue's tail.  When the buffer's end is reached the
-// queued entries move to its start (or to a buffer twice as large).
+// Appends chunks at the queue's tail.  When the ring could overflow, the
+// worker waits for the device, reads its head and, if still short of room,
+// moves the queued entries to a ring twice as large (same positions).
 cosmica_status ring_append(ServeGroup* g, const std::vector<ChunkDev>& ch)
 {
     cosmica_ctx* ctx = g->ctx;
     hipStream_t s = ctx->serve_stream;
-    const uint64_t n = ch.size(), live = g->q_tail - g->q_head;
-    if (g->q_tail + n > g->ring_cap) {
-        uint64_t cap = g->ring_cap;
-        while (live + n > cap / 2) cap *= 2;  // room to spare after the move
-        ChunkDev* dst = g->ring_d;
-        if (cap != g->ring_cap) {
+    const uint64_t n = ch.size();
+    if (n == 0) return COSMICA_OK;
+    if (g->q_tail + n - g->q_head > g->ring_cap) {
+        HIP_TRY(hipStreamSynchronize(s));
+        uint64_t head = 0;
+        HIP_TRY(hipMemcpy(&head, g->ctl_d, sizeof(head), hipMemcpyDeviceToHost));
+        g->q_head = head;
+        const uint64_t live = g->q_tail - g->q_head;
+        if (live + n > g->ring_cap) {
+            uint64_t cap = g->ring_cap;
+            while (live + n > cap / 2) cap *= 2;
+            ChunkDev* dst = nullptr;
             cosmica_status st = dalloc(ctx, cap * sizeof(ChunkDev), (void**)&dst);
             if (st != COSMICA_OK) return st;
-        }
-        if (live > 0) {
-            if (dst != g->ring_d || live <= g->q_head) {
-                // source and destination do not overlap
-                HIP_TRY(hipMemcpyAsync(dst, g->ring_d + g->q_head, live * sizeof(ChunkDev),
+            for (uint64_t pos = g->q_head; pos < g->q_tail;) {
+                const uint64_t from = pos & (g->ring_cap - 1), to = pos & (cap - 1);
+                const uint64_t len =
+                    std::min({g->q_tail - pos, g->ring_cap - from, cap - to});
+                HIP_TRY(hipMemcpyAsync(dst + to, g->ring_d + from, len * sizeof(ChunkDev),
                                        hipMemcpyDeviceToDevice, s));
-            } else {
-                std::vector<ChunkDev> tmp(live);
-                HIP_TRY(hipMemcpyAsync(tmp.data(), g->ring_d + g->q_head, live * sizeof(ChunkDev),
-                                       hipMemcpyDeviceToHost, s));
-                HIP_TRY(hipStreamSynchronize(s));
-                HIP_TRY(hipMemcpyAsync(dst, tmp.data(), live * sizeof(ChunkDev),
-                                       hipMemcpyHostToDevice, s));
+                pos += len;
             }
-        }
-        HIP_TRY(hipStreamSynchronize(s));
-        if (dst != g->ring_d) {
+            HIP_TRY(hipStreamSynchronize(s));
             dfree(ctx, g->ring_d, g->ring_cap * sizeof(ChunkDev));
             g->ring_d = dst;
             g->ring_cap = cap;
         }
-        g->q_head = 0;
-        g->q_tail = live;
     }
-    if (n > 0)
-        HIP_TRY(hipMemcpyAsync(g->ring_d + g->q_tail, ch.data(), n * sizeof(ChunkDev),
-                               hipMemcpyHostToDevice, s));
+    for (uint64_t k = 0; k < n;) {
+        const uint64_t at = (g->q_tail + k) & (g->ring_cap - 1);
+        const uint64_t len = std::min(n - k, g->ring_cap - at);
+        cosmica_status st = upload(ctx, g->ring_d + at, ch.data() + k, len * sizeof(ChunkDev));
+        if (st != COSMICA_OK) return st;
+        k += len;
+    }
     g->q_tail += n;
-    // pageable source: the copy must be complete before the vector goes
-    HIP_TRY(hipStreamSynchronize(s));
     return COSMICA_OK;
 }
 
@@ -2190,30 +2309,29 @@ cosmica_status upload_slot(ServeGroup* g, Req* q)
     RegionDev<R> reg[kRegionStride];
     LisDev lis;
     make_tables<R>(head_of(q->job), &J, reg, &lis);
-    hipStream_t s = g->ctx->serve_stream;
+    cosmica_ctx* ctx = g->ctx;
     const int slot = q->slot;
     J.orbit_off = (uint32_t)slot * COSMICA_MAX_ORBIT;
     std::vector<OrbitDev> oh;
     const std::vector<double>& o = q->job.orbit;
     for (size_t k = 0; k + 2 < o.size(); k += 3) oh.push_back(OrbitDev{o[k], o[k + 1], o[k + 2], 0.0});
-    if (!oh.empty())
-        HIP_TRY(hipMemcpyAsync(g->orbit_d + J.orbit_off, oh.data(), oh.size() * sizeof(OrbitDev),
-                               hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync((JobDev<R>*)g->jobs_d + slot, &J, sizeof(J), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync((RegionDev<R>*)g->regions_d + (size_t)slot * kRegionStride, reg,
-                           sizeof(reg), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(g->lis_d + slot, &lis, sizeof(lis), hipMemcpyHostToDevice, s));
+    cosmica_status st;
+    if ((st = upload(ctx, g->orbit_d + J.orbit_off, oh.data(), oh.size() * sizeof(OrbitDev))) !=
+        COSMICA_OK)
+        return st;
+    if ((st = upload(ctx, (JobDev<R>*)g->jobs_d + slot, &J, sizeof(J))) != COSMICA_OK) return st;
+    if ((st = upload(ctx, (RegionDev<R>*)g->regions_d + (size_t)slot * kRegionStride, reg,
+                     sizeof(reg))) != COSMICA_OK)
+        return st;
+    if ((st = upload(ctx, g->lis_d + slot, &lis, sizeof(lis))) != COSMICA_OK) return st;
     const size_t s0 = (size_t)slot * ServeGroup::kBinsPerSlot;
-    HIP_TRY(hipMemcpyAsync(g->segs_d + s0, &g->segs_h[s0],
-                           q->job.rig.size() * sizeof(SegmentDev), hipMemcpyHostToDevice, s));
-    // pageable host sources: wait so the staging copies are complete
-    HIP_TRY(hipStreamSynchronize(s));
-    return COSMICA_OK;
+    return upload(ctx, g->segs_d + s0, &g->segs_h[s0], q->job.rig.size() * sizeof(SegmentDev));
 }
 
 // Admit queued requests (FIFO) while a slot and a contiguous exit-record range fit.
 cosmica_status admit(cosmica_ctx* ctx)
 {
+    hipStream_t s = ctx->serve_stream;
     while (!ctx->queued.empty()) {
         Req* q = ctx->queued.front();
         if (q->cancel) {
@@ -2259,13 +2377,13 @@ cosmica_status admit(cosmica_ctx* ctx)
         uint64_t o = off;
         std::vector<uint32_t> ids;
         for (size_t b = 0; b < q->job.rig.size(); ++b) {
-            SegmentDev& s = g->segs_h[s0 + b];
-            std::memset(&s, 0, sizeof(s));
-            s.P0 = q->job.rig[b];
-            s.job = (uint32_t)q->slot;
-            s.bin = q->job.bin_offset + (uint32_t)b;
-            s.count = q->job.cnt[b];
-            s.out_offset = (uint32_t)o;
+            SegmentDev& sg = g->segs_h[s0 + b];
+            std::memset(&sg, 0, sizeof(sg));
+            sg.P0 = q->job.rig[b];
+            sg.job = (uint32_t)q->slot;
+            sg.bin = q->job.bin_offset + (uint32_t)b;
+            sg.count = q->job.cnt[b];
+            sg.out_offset = (uint32_t)o;
             o += q->job.cnt[b];
             ids.push_back((uint32_t)(s0 + b));
         }
@@ -2280,95 +2398,70 @@ cosmica_status admit(cosmica_ctx* ctx)
         make_chunks(g->segs_h, ids, L.chunk, L.order, &chunks, &cost);
         cosmica_status st = q->prec == 1 ? upload_slot<float>(g, q) : upload_slot<double>(g, q);
         if (st != COSMICA_OK) return st;
-        g->slot_cancelled[q->slot] = 0;
+        // the slot's counters start again (stream-ordered after every slice
+        // enqueued so far, before the request's first one)
+        HIP_TRY(launch_fill_u32(g->ctl_d + ServeGroup::kCtlDone + q->slot, 0u, 1, s));
+        HIP_TRY(launch_fill_u32(g->cancel_d + q->slot, 0u, 1, s));
         if ((st = ring_append(g, chunks)) != COSMICA_OK) return st;
         q->ring_end = g->q_tail;
-        uint32_t zero = 0;
-        HIP_TRY(hipMemcpy(g->done_d + q->slot, &zero, 4, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(g->cancel_d + q->slot, &zero, 4, hipMemcpyHostToDevice));
+        q->first_slice = g->seq;
         q->state = 1;
         g->resident.push_back(q);
     }
     return COSMICA_OK;
 }
 
+// Enqueues one slice of a group: the propagation kernel, the closing kernel,
+// and the copy of the control words to the host.
 template <typename R>
 cosmica_status launch_slice(ServeGroup* g)
 {
     cosmica_ctx* ctx = g->ctx;
     hipStream_t s = ctx->serve_stream;
-    const uint32_t nch = (uint32_t)std::min<uint64_t>(g->q_tail - g->q_head, 0xffffffffu);
-    HIP_TRY(launch_fill_u32(g->counters_d, 0u, 8, s));
+    const int p = (int)(g->seq & 1u), o = p ^ 1;
+    uint32_t* c = g->ctl_d;
     PropArgs<R> a;
     std::memset(&a, 0, sizeof(a));
     a.jobs = (const JobDev<R>*)g->jobs_d;
     a.regions = (const RegionDev<R>*)g->regions_d;
     a.orbit = g->orbit_d;
     a.segs = g->segs_d;
-    a.chunks = g->ring_d + g->q_head;
-    a.n_chunks = nch;
-    a.head = g->counters_d + 0;
+    a.chunks = g->ring_d;
+    a.head = (unsigned long long*)c;
+    a.q_tail = g->q_tail;
+    a.q_mask = g->ring_cap - 1;
     a.exP = g->exP;
     a.exT = g->exT;
     a.exNF = g->exNF;
-    a.resume = g->susp[g->cur];
-    a.n_resume = g->n_resume;
-    a.resume_head = g->counters_d + 1;
-    a.suspend = g->susp[g->cur ^ 1];
-    a.suspend_count = g->counters_d + 2;
+    a.exL = g->exL;
+    a.slice = g->slice_d + p;
     a.step_budget = slice_steps();
     a.slice_ticks = slice_ticks(ctx);
     if (a.step_budget == 0xffffffffu && a.slice_ticks == 0) a.step_budget = 2048u;
     a.job_cancel = g->cancel_d;
-    a.job_done = g->done_d;
-    a.leftover = g->left_d;
-    a.leftover_count = g->counters_d + 3;
+    a.job_done = c + ServeGroup::kCtlDone;
     // every request holding a slot may have particles in this slice
     for (const Req* q : g->resident) a.shaped |= job_shaped(q->job) ? 1u : 0u;
     for (const Req* q : g->releasing) a.shaped |= job_shaped(q->job) ? 1u : 0u;
     for (const Req* q : g->resident) a.energy |= q->job.formulation == 1 ? 1u : 0u;
     for (const Req* q : g->releasing) a.energy |= q->job.formulation == 1 ? 1u : 0u;
-    a.exL = g->exL;
-    g->n_chunks_last = nch;
-    // A wave claims parked particles only until its step budget is spent, so a
-    // slice must hold at least as many lanes as there are parked particles, or
-    // the unclaimed ones would never come back.  The kernel variants for a
-    // squashed heliosphere or the energy form fit fewer waves per CU than the
-    // variant whose slice parked them: such a slice gets the workgroups beyond
-    // residency too; they start as the first ones finish their budget.
-    const int vgrid = g->grid_var[(a.shaped ? 1 : 0) | (a.energy ? 2 : 0)];
-    const int need = (int)(((uint64_t)g->n_resume + (uint64_t)g->block - 1) / (uint64_t)g->block);
-    HIP_TRY(launch_model<R>(g->model, a, std::max(vgrid, need), g->block, s));
-    return COSMICA_OK;
-}
-
-cosmica_status collect_slice(ServeGroup* g)
-{
-    hipStream_t s = g->ctx->serve_stream;
-    uint32_t c[4];  // chunk cursor, resume cursor, parked count, unfinished chunks
-    HIP_TRY(hipMemcpy(c, g->counters_d, sizeof(c), hipMemcpyDeviceToHost));
-    // every parked particle of the previous slice was taken up (the slice
-    // launched at least one lane per parked particle)
-    if (c[1] < g->n_resume) return COSMICA_EDEVICE;
-    g->q_head += std::min(c[0], g->n_chunks_last);
-    // chunks waves held unfinished go back in front of the queue (they were
-    // issued from this slice's part of it, so the room before q_head is free),
-    // except those of cancelled requests
-    if (c[3]) {
-        std::vector<ChunkDev> left(c[3]), keep;
-        HIP_TRY(hipMemcpy(left.data(), g->left_d, c[3] * sizeof(ChunkDev), hipMemcpyDeviceToHost));
-        for (const ChunkDev& ch : left)
-            if (!g->slot_cancelled[ch.seg / ServeGroup::kBinsPerSlot]) keep.push_back(ch);
-        if (keep.size() > g->q_head) return COSMICA_EDEVICE;
-        g->q_head -= keep.size();
-        if (!keep.empty()) {
-            HIP_TRY(hipMemcpyAsync(g->ring_d + g->q_head, keep.data(), keep.size() * sizeof(ChunkDev),
-                                   hipMemcpyHostToDevice, s));
-            HIP_TRY(hipStreamSynchronize(s));
-        }
-    }
-    g->n_resume = c[2];
-    g->cur ^= 1;
+    // The variants for a squashed heliosphere or the energy form may fit fewer
+    // lanes than the previous slice parked particles: the closing kernel
+    // carries what no wave claimed over to the next slice.
+    const int grid = g->grid_var[(a.shaped ? 1 : 0) | (a.energy ? 2 : 0)];
+    HIP_TRY(launch_model<R>(g->model, a, grid, g->block, s));
+    CloseArgs k;
+    std::memset(&k, 0, sizeof(k));
+    k.sl = g->slice_h[p];
+    k.head = a.head;
+    k.q_tail = g->q_tail;
+    k.segs = g->segs_d;
+    k.job_cancel = g->cancel_d;
+    k.next_counters = c + ServeGroup::park_word(o, 0);
+    HIP_TRY(launch_slice_close(k, s));
+    HIP_TRY(hipMemcpyAsync(g->snap_h + (size_t)p * ServeGroup::kCtlWords, c,
+                           ServeGroup::kCtlWords * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    ++g->seq;
     return COSMICA_OK;
 }
 
@@ -2379,10 +2472,13 @@ void release(ServeGroup* g, Req* q)
     q->slot = -1;
 }
 
-// Reduce a finished request's bins and copy results to its buffers.
+// Enqueues the reduction of a finished request's bins and the copy of its
+// results to pinned memory; the slot and the exit records go back at once
+// (what is enqueued later on the stream runs after these copies).
 cosmica_status finish_request(ServeGroup* g, Req* q)
 {
     cosmica_ctx* ctx = g->ctx;
+    ServeHost& H = *ctx->serve_host;
     hipStream_t s = ctx->serve_stream;
     const uint32_t nb = (uint32_t)q->job.rig.size();
     ReduceArgs r;
@@ -2403,18 +2499,38 @@ cosmica_status finish_request(ServeGroup* g, Req* q)
     r.n_capped = g->r_ncap;
     r.n_nan = g->r_nnan;
     HIP_TRY(launch_reduce(r, nb, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    if (H.free_blocks.empty()) {
+        unsigned char* b = nullptr;
+        HIP_TRY(hipHostMalloc((void**)&b, ServeHost::kResultBytes, hipHostMallocDefault));
+        H.blocks.push_back(b);
+        H.free_blocks.push_back(b);
+    }
+    if (H.free_events.empty()) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        H.events.push_back(e);
+        H.free_events.push_back(e);
+    }
+    q->staged = H.free_blocks.back();
+    H.free_blocks.pop_back();
+    q->staged_ev = H.free_events.back();
+    H.free_events.pop_back();
+    unsigned char* b = q->staged;
+    HIP_TRY(hipMemcpyAsync(b, g->r_hist, (size_t)nb * kNHist * 4, hipMemcpyDeviceToHost, s));
+    b += (size_t)nb * kNHist * 4;
+    const void* src8[4] = {g->r_flux, g->r_se, g->r_mt, g->r_steps};
+    for (const void* p : src8) {
+        HIP_TRY(hipMemcpyAsync(b, p, (size_t)nb * 8, hipMemcpyDeviceToHost, s));
+        b += (size_t)nb * 8;
+    }
+    HIP_TRY(hipMemcpyAsync(b, g->r_ncap, (size_t)nb * 4, hipMemcpyDeviceToHost, s));
+    b += (size_t)nb * 4;
+    HIP_TRY(hipMemcpyAsync(b, g->r_nnan, (size_t)nb * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(q->staged_ev, s));
     const cosmica_result& R = q->res;
-    std::vector<uint32_t> ncap(nb);
-    HIP_TRY(hipMemcpy(ncap.data(), g->r_ncap, nb * 4, hipMemcpyDeviceToHost));
-    if (R.hist) HIP_TRY(hipMemcpy(R.hist, g->r_hist, (size_t)nb * kNHist * 4, hipMemcpyDeviceToHost));
-    if (R.flux) HIP_TRY(hipMemcpy(R.flux, g->r_flux, nb * 8, hipMemcpyDeviceToHost));
-    if (R.flux_se) HIP_TRY(hipMemcpy(R.flux_se, g->r_se, nb * 8, hipMemcpyDeviceToHost));
-    if (R.mean_exit_time_s) HIP_TRY(hipMemcpy(R.mean_exit_time_s, g->r_mt, nb * 8, hipMemcpyDeviceToHost));
-    if (R.steps) HIP_TRY(hipMemcpy(R.steps, g->r_steps, nb * 8, hipMemcpyDeviceToHost));
-    if (R.n_capped) std::memcpy(R.n_capped, ncap.data(), nb * 4);
-    if (R.n_nan) HIP_TRY(hipMemcpy(R.n_nan, g->r_nnan, nb * 4, hipMemcpyDeviceToHost));
     if (R.exits) {
+        // exit records go straight to the caller's (pageable) array
+        HIP_TRY(hipStreamSynchronize(s));
         const size_t n = q->job.total;
         std::vector<double> P(n), T(n), Ls(n, 0.0);
         std::vector<uint32_t> NF(n);
@@ -2433,17 +2549,100 @@ cosmica_status finish_request(ServeGroup* g, Req* q)
             e.flags = NF[i] >> kFlagShift;
         }
     }
-    bool capped = false;
-    for (uint32_t v : ncap) capped |= v > 0;
-    q->status = capped ? COSMICA_ESTEPCAP : COSMICA_OK;
+    release(g, q);
+    H.finishing.push_back(q);
+    return COSMICA_OK;
+}
+
+// Hands the staged results of finished requests to their callers: those whose
+// copies are done (all of them, waiting, if wait is set).
+cosmica_status deliver(cosmica_ctx* ctx, bool wait)
+{
+    ServeHost& H = *ctx->serve_host;
+    for (auto it = H.finishing.begin(); it != H.finishing.end();) {
+        Req* q = *it;
+        hipError_t e = wait ? hipEventSynchronize(q->staged_ev) : hipEventQuery(q->staged_ev);
+        if (e == hipErrorNotReady) {
+            ++it;
+            continue;
+        }
+        if (e != hipSuccess) return COSMICA_EDEVICE;
+        const uint32_t nb = (uint32_t)q->job.rig.size();
+        const cosmica_result& R = q->res;
+        const unsigned char* b = q->staged;
+        if (R.hist) std::memcpy(R.hist, b, (size_t)nb * kNHist * 4);
+        b += (size_t)nb * kNHist * 4;
+        double* dst8[3] = {R.flux, R.flux_se, R.mean_exit_time_s};
+        for (double* d : dst8) {
+            if (d) std::memcpy(d, b, (size_t)nb * 8);
+            b += (size_t)nb * 8;
+        }
+        if (R.steps) std::memcpy(R.steps, b, (size_t)nb * 8);
+        b += (size_t)nb * 8;
+        const uint32_t* ncap = (const uint32_t*)b;
+        if (R.n_capped) std::memcpy(R.n_capped, ncap, (size_t)nb * 4);
+        b += (size_t)nb * 4;
+        if (R.n_nan) std::memcpy(R.n_nan, b, (size_t)nb * 4);
+        bool capped = false;
+        for (uint32_t k = 0; k < nb; ++k) capped |= ncap[k] > 0;
+        q->status = capped ? COSMICA_ESTEPCAP : COSMICA_OK;
+        q->state = 2;
+        H.free_blocks.push_back(q->staged);
+        H.free_events.push_back(q->staged_ev);
+        q->staged = nullptr;
+        q->staged_ev = nullptr;
+        it = H.finishing.erase(it);
+        ctx->cv.notify_all();
+    }
+    return COSMICA_OK;
+}
+
+// What slice `seq` of a group did, from its copy of the control words:
+// requests whose particles have all exited are finished, and cancelled ones
+// are freed once none of their work is left on the device.
+cosmica_status read_slice(ServeGroup* g, uint64_t seq)
+{
+    const int p = (int)(seq & 1u);
+    const uint32_t* c = g->snap_h + (size_t)p * ServeGroup::kCtlWords;
+    if (c[ServeGroup::kCtlOverflow] != 0u) return COSMICA_EDEVICE;
+    g->q_head = (uint64_t)c[0] | ((uint64_t)c[1] << 32);
+    g->in_flight = c[ServeGroup::park_word(p, 0)];
+    for (auto it = g->resident.begin(); it != g->resident.end();) {
+        Req* q = *it;
+        if (q->first_slice <= seq && c[ServeGroup::kCtlDone + q->slot] >= q->job.total) {
+            cosmica_status st = finish_request(g, q);
+            if (st != COSMICA_OK) return st;
+            it = g->resident.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    // A slice that sees a cancel flag drops the request's parked particles and
+    // chunk remainders (claimed or not), and every chunk issued from then on;
+    // so after such a slice, with the head past the request's last chunk,
+    // nothing of it is left.
+    for (auto it = g->releasing.begin(); it != g->releasing.end();) {
+        Req* q = *it;
+        if (q->cancel_slice <= seq && g->q_head >= q->ring_end) {
+            release(g, q);
+            it = g->releasing.erase(it);
+        } else {
+            ++it;
+        }
+    }
     return COSMICA_OK;
 }
 
 void serve_loop(cosmica_ctx* ctx)
 {
     (void)hipSetDevice(ctx->device);
+    ServeHost& H = *ctx->serve_host;
+    std::vector<std::pair<ServeGroup*, uint64_t>> prev, cur;  // (group, slice) per round
+    uint64_t round = 0;
     std::unique_lock<std::mutex> lk(ctx->mu);
     while (!ctx->stop) {
+        H.cur = (int)(round & 1u);
+        H.used = 0;
         cosmica_status st = admit(ctx);
         if (st != COSMICA_OK) {
             ctx->serve_error = st;
@@ -2453,90 +2652,79 @@ void serve_loop(cosmica_ctx* ctx)
         for (int m = 0; m < 2; ++m)
             for (int q = 0; q < 2; ++q) {
                 ServeGroup* g = ctx->groups[m][q].get();
-                if (g && (!g->resident.empty() || g->n_resume || !g->releasing.empty() ||
-                          g->q_head < g->q_tail))
-                    active.push_back(g);
+                if (g == nullptr) continue;
+                // cancellations: a flag on the device, set before the next slice
+                for (auto it = g->resident.begin(); it != g->resident.end();) {
+                    Req* r = *it;
+                    if (r->cancel && !r->cancel_sent) {
+                        if (launch_fill_u32(g->cancel_d + r->slot, 1u, 1, ctx->serve_stream) !=
+                            hipSuccess)
+                            ctx->serve_error = COSMICA_EDEVICE;
+                        r->cancel_sent = true;
+                        r->cancel_slice = g->seq;
+                        r->state = 2;
+                        r->status = COSMICA_ECANCELED;
+                        g->releasing.push_back(r);
+                        it = g->resident.erase(it);
+                        ctx->cv.notify_all();
+                    } else {
+                        ++it;
+                    }
+                }
+                if (!g->resident.empty() || !g->releasing.empty()) active.push_back(g);
             }
-        if (active.empty()) {
+        if (ctx->serve_error != COSMICA_OK) break;
+        if (active.empty() && prev.empty()) {
+            if (!H.finishing.empty()) {
+                lk.unlock();
+                const hipError_t e = hipStreamSynchronize(ctx->serve_stream);
+                lk.lock();
+                if (e != hipSuccess || (st = deliver(ctx, false)) != COSMICA_OK) {
+                    ctx->serve_error = COSMICA_EDEVICE;
+                    break;
+                }
+                continue;
+            }
             ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->queued.empty(); });
             continue;
         }
-        // cancellations: flag on the device, drop unissued chunks
-        for (ServeGroup* g : active) {
-            for (auto it = g->resident.begin(); it != g->resident.end();) {
-                Req* q = *it;
-                if (q->cancel && !q->cancel_sent) {
-                    uint32_t one = 1;
-                    if (hipMemcpy(g->cancel_d + q->slot, &one, 4, hipMemcpyHostToDevice) !=
-                        hipSuccess)
-                        ctx->serve_error = COSMICA_EDEVICE;
-                    // its queued chunks are dropped as they are issued (the
-                    // kernel skips particles of cancelled jobs)
-                    g->slot_cancelled[q->slot] = 1;
-                    q->cancel_sent = true;
-                    q->state = 2;
-                    q->status = COSMICA_ECANCELED;
-                    g->releasing.push_back(q);
-                    it = g->resident.erase(it);
-                    ctx->cv.notify_all();
-                } else {
-                    ++it;
-                }
-            }
-        }
         lk.unlock();
         bool ok = true;
+        cur.clear();
         for (ServeGroup* g : active) {
             st = g->prec == 1 ? launch_slice<float>(g) : launch_slice<double>(g);
             ok &= st == COSMICA_OK;
+            cur.emplace_back(g, g->seq - 1);
         }
-        if (ok && hipStreamSynchronize(ctx->serve_stream) != hipSuccess) ok = false;
-        std::vector<uint32_t> done(ServeGroup::kSlots);
+        // the device now holds this round's slices: read what the previous
+        // round's did while they run
+        if (ok && hipEventRecord(H.round_ev[round & 1u], ctx->serve_stream) != hipSuccess) ok = false;
+        if (ok && !prev.empty() && hipEventSynchronize(H.round_ev[(round - 1) & 1u]) != hipSuccess)
+            ok = false;
         lk.lock();
         if (!ok) {
             ctx->serve_error = COSMICA_EDEVICE;
             break;
         }
-        for (ServeGroup* g : active) {
-            if (collect_slice(g) != COSMICA_OK ||
-                hipMemcpy(done.data(), g->done_d, done.size() * 4, hipMemcpyDeviceToHost) !=
-                    hipSuccess) {
-                ctx->serve_error = COSMICA_EDEVICE;
+        // results copied after the previous round's slices are next in the
+        // stream (this round's slices queue behind them): a short wait
+        if ((st = deliver(ctx, true)) != COSMICA_OK) {
+            ctx->serve_error = st;
+            break;
+        }
+        for (auto& gs : prev)
+            if ((st = read_slice(gs.first, gs.second)) != COSMICA_OK) {
+                ctx->serve_error = st;
                 ok = false;
                 break;
             }
-            // a cancelled request's slot and records are freed once the queue has
-            // issued all its chunks and a slice has dropped its parked particles
-            for (auto it = g->releasing.begin(); it != g->releasing.end();) {
-                Req* q = *it;
-                if (g->q_head >= q->ring_end) {
-                    uint32_t zero = 0;
-                    (void)hipMemcpy(g->cancel_d + q->slot, &zero, 4, hipMemcpyHostToDevice);
-                    release(g, q);
-                    it = g->releasing.erase(it);
-                } else {
-                    ++it;
-                }
-            }
-            for (auto it = g->resident.begin(); it != g->resident.end();) {
-                Req* q = *it;
-                if (done[q->slot] >= q->job.total) {
-                    if (finish_request(g, q) != COSMICA_OK) {
-                        ctx->serve_error = COSMICA_EDEVICE;
-                        ok = false;
-                    }
-                    release(g, q);
-                    q->state = 2;
-                    it = g->resident.erase(it);
-                    ctx->cv.notify_all();
-                } else {
-                    ++it;
-                }
-            }
-        }
         if (!ok) break;
+        prev.swap(cur);
+        ++round;
     }
-    // fail whatever is left so waiters return
+    // results already on their way are handed over; whatever is left fails so
+    // waiters return
+    if (ctx->serve_error == COSMICA_OK) (void)deliver(ctx, true);
     for (auto& kv : ctx->reqs)
         if (kv.second->state != 2) {
             kv.second->state = 2;
@@ -2570,6 +2758,11 @@ cosmica_status cosmica_submit(cosmica_ctx* ctx, const cosmica_job* job,
         if (hipSetDevice(ctx->device) != hipSuccess ||
             hipStreamCreateWithFlags(&ctx->serve_stream, hipStreamNonBlocking) != hipSuccess)
             return COSMICA_EDEVICE;
+        if (serve_host_init(ctx) != COSMICA_OK) {
+            (void)hipStreamDestroy(ctx->serve_stream);
+            ctx->serve_stream = nullptr;
+            return COSMICA_EDEVICE;
+        }
         ctx->worker = std::thread(serve_loop, ctx);
         ctx->worker_started = true;
     }
@@ -2637,7 +2830,7 @@ cosmica_status cosmica_serve_stats(cosmica_ctx* ctx, uint64_t* queued, uint64_t*
         for (int q = 0; q < 2; ++q)
             if (ctx->groups[m][q]) {
                 res += ctx->groups[m][q]->resident.size();
-                fl += ctx->groups[m][q]->n_resume;
+                fl += ctx->groups[m][q]->in_flight;
             }
     if (queued) *queued = ctx->queued.size();
     if (resident) *resident = res;
