@@ -356,6 +356,30 @@ def plain_leg(eng, pjobs, sync, scale, mixed=None) -> dict:
     return out
 
 
+def saturated_leg(eng, seconds, capacity, batched_rate):
+    """The config-5 request mix offered at twice the device's capacity (requests
+    /s): served steps/s over the whole leg and in steady state, against the
+    batched rate and against the same requests run as one batched pass."""
+    sat = serve(eng, seconds, 2.0 * capacity, "mixed", seed=44, cut_at=seconds, poll_s=0.02)
+    sat["offered_over_capacity"] = 2.0
+    sat["capacity_req_s"] = round(capacity, 2)
+    sat["frac_of_peak"] = round(sum(OPS_PER_STEP["3d"].values()) * sat["steps_per_s"]
+                                / 1e12 / PEAK_TOPS["mixed"], 4)
+    sat["served_over_batched"] = round(sat["steps_per_s"] / batched_rate, 4)
+    sat["steady_over_batched"] = round(sat["steady_steps_per_s"] / batched_rate, 4)
+    # the same request mix as one batched pass (the stream's first 120
+    # requests): served over batched on work of one kind
+    same = [r["job"] for r in W.c5_requests(seed=44, rate_hz=2.0 * capacity, duration_s=seconds,
+                                             max_requests=120)]
+    eng.run(same, "mixed")
+    t = eng.timings()
+    same_rate = t["steps"] / (t["propagate_ms"] * 1e-3)
+    sat["batched_same_requests"] = {"requests": len(same), "steps": int(t["steps"]),
+                                    "steps_per_s": same_rate}
+    sat["steady_over_same_batched"] = round(sat["steady_steps_per_s"] / same_rate, 4)
+    return sat
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -381,12 +405,17 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
                     help="time the batched pass only (profiling runs)")
+    ap.add_argument("--saturated-only", action="store_true",
+                    help="the batched pass, then only the saturated serving leg at "
+                         "--saturate-rate requests/s (profiling runs)")
+    ap.add_argument("--saturate-rate", type=float, default=50.0,
+                    help="offered request rate of --saturated-only (about twice capacity)")
     ap.add_argument("--default-launch", action="store_true",
                     help="skip the tuner: the library's default launch shape (quick runs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
-    if args.batched_only or args.heliosheath_only or args.plain_only:
+    if args.batched_only or args.heliosheath_only or args.plain_only or args.saturated_only:
         args.no_plain = args.no_serve = args.no_cpu = True
         args.no_heliosheath = args.no_orbit = args.no_energy = args.no_reweight = True
     if args.gpus != 1:
@@ -456,6 +485,12 @@ def main():
         reweight["exit_range_128_ms"] = round((time.perf_counter() - t0) / 3 * 1e3, 3)
         log("exit range:", reweight["exit_range_128_ms"], "ms")
     plan.destroy()
+    if args.saturated_only:
+        sat = saturated_leg(eng, args.saturate_seconds, args.saturate_rate / 2.0, value)
+        log("serving saturated:", sat)
+        print(json.dumps({"batched_steps_per_s": value, "saturated_mixed": sat}), flush=True)
+        eng.close()
+        return
 
     ops = sum(OPS_PER_STEP["3d"].values())
     steps_per_launch = nsteps[-1]
@@ -498,25 +533,7 @@ def main():
         m = serving["mixed"]
         steps_per_req = m["steps_per_s"] * m["seconds"] / max(1, m["completed"])
         capacity = value / steps_per_req  # requests/s the batched rate would absorb
-        sat = serve(eng, args.saturate_seconds, 2.0 * capacity, "mixed", seed=44,
-                    cut_at=args.saturate_seconds, poll_s=0.02)
-        sat["offered_over_capacity"] = 2.0
-        sat["capacity_req_s"] = round(capacity, 2)
-        sat["frac_of_peak"] = round(sum(OPS_PER_STEP["3d"].values()) * sat["steps_per_s"]
-                                    / 1e12 / PEAK_TOPS["mixed"], 4)
-        sat["served_over_batched"] = round(sat["steps_per_s"] / value, 4)
-        sat["steady_over_batched"] = round(sat["steady_steps_per_s"] / value, 4)
-        # the same request mix as one batched pass (the stream's first 120
-        # requests): served over batched on work of one kind
-        same = [r["job"] for r in W.c5_requests(seed=44, rate_hz=2.0 * capacity,
-                                                 duration_s=args.saturate_seconds,
-                                                 max_requests=120)]
-        eng.run(same, "mixed")
-        t = eng.timings()
-        same_rate = t["steps"] / (t["propagate_ms"] * 1e-3)
-        sat["batched_same_requests"] = {"requests": len(same), "steps": int(t["steps"]),
-                                        "steps_per_s": same_rate}
-        sat["steady_over_same_batched"] = round(sat["steady_steps_per_s"] / same_rate, 4)
+        sat = saturated_leg(eng, args.saturate_seconds, capacity, value)
         serving["saturated_mixed"] = sat
         log("serving saturated:", sat)
     eng.close()
