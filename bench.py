@@ -136,14 +136,17 @@ def time_plan(eng, plan, steps, warmup, sync, first=None):
     return wall, prop, red, nsteps, t
 
 
-def serve(eng, seconds, rate, precision, seed=42, cut_at=None, poll_s=0.002):
+def serve(eng, seconds, rate, precision, seed=42, cut_at=None, poll_s=0.002, warmup_s=0.0,
+          progress_s=None):
     """Replay a Poisson stream of spectrum requests (the config-5 request mix);
     latency = arrival -> result on the host.  cut_at: cancel the requests still
     waiting for admission at that time (a saturated stream), so the leg ends
     once the admitted ones finish; they are counted apart.  A saturated leg also
     reports its steady rate: the steps of the requests completed between a
     quarter of the arrival window and the cut, over that time (the whole-leg
-    rate includes the ramp at the start and the drain after the cut)."""
+    rate includes the ramp at the start and the drain after the cut).  warmup_s:
+    requests arriving before it are served but left out of the statistics;
+    progress_s: a progress line on stderr that often."""
     reqs = W.c5_requests(seed=seed, rate_hz=rate, duration_s=seconds)
     tickets = []
     lat = []
@@ -167,6 +170,7 @@ def serve(eng, seconds, rate, precision, seed=42, cut_at=None, poll_s=0.002):
     cut = False
     last_done = t0
     completions = []  # (seconds since t0, steps) per completed request
+    next_progress = progress_s
     while not (done.is_set() and finished + cancelled == len(tickets)):
         while n_seen < len(tickets):
             pending.append(tickets[n_seen])
@@ -192,16 +196,21 @@ def serve(eng, seconds, rate, precision, seed=42, cut_at=None, poll_s=0.002):
                 if st == C.ECANCELED:
                     cancelled += 1
                 else:
-                    lat.append(time.perf_counter() - t0 - arr)
-                    n = int(tk.result()["steps"].sum())
-                    steps += n
-                    completions.append((time.perf_counter() - t0, n))
                     finished += 1
-                    last_done = time.perf_counter()
+                    if arr >= warmup_s:
+                        lat.append(time.perf_counter() - t0 - arr)
+                        n = int(tk.result()["steps"].sum())
+                        steps += n
+                        completions.append((time.perf_counter() - t0, n))
+                        last_done = time.perf_counter()
                 pending[i] = (arr, None)
+        if next_progress is not None and time.perf_counter() - t0 >= next_progress:
+            log(f"serving {precision}: {time.perf_counter() - t0:.0f} s, {len(tickets)} submitted, "
+                f"{finished} finished")
+            next_progress += progress_s
         time.sleep(poll_s)
     th.join()
-    span = last_done - t0
+    span = last_done - t0 - warmup_s
     lat = np.array(lat)
     pct = lambda q: round(float(np.percentile(lat, q)), 3) if len(lat) else None
     out = {
@@ -209,9 +218,13 @@ def serve(eng, seconds, rate, precision, seed=42, cut_at=None, poll_s=0.002):
         "requests": len(reqs), "completed": finished, "seconds": round(span, 2),
         "p50_latency_s": pct(50), "p90_latency_s": pct(90), "p99_latency_s": pct(99),
         "max_latency_s": pct(100),
-        "spectra_per_hour": round(finished / span * 3600.0, 1),
+        "spectra_per_hour": round(len(lat) / span * 3600.0, 1),
         "steps_per_s": float(steps / span),
     }
+    if warmup_s > 0:
+        out["warmup_seconds"] = warmup_s
+        out["measured_requests"] = len(lat)
+        out["p99_9_latency_s"] = pct(99.9)
     if cut_at is not None:
         out["cancelled_unadmitted"] = cancelled
         w0, w1 = 0.25 * cut_at, cut_at
@@ -410,6 +423,11 @@ def main():
                          "--saturate-rate requests/s (profiling runs)")
     ap.add_argument("--saturate-rate", type=float, default=50.0,
                     help="offered request rate of --saturated-only (about twice capacity)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only the config-5 stream, --serve-seconds of arrivals after "
+                         "--serve-warmup seconds, in the --serve-precisions")
+    ap.add_argument("--serve-warmup", type=float, default=0.0)
+    ap.add_argument("--serve-precisions", default="mixed,fp64")
     ap.add_argument("--default-launch", action="store_true",
                     help="skip the tuner: the library's default launch shape (quick runs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -436,6 +454,20 @@ def main():
         log(f"copy calibration: {args.copy_calibration_mib} MiB read + written")
         del src, dst
     eng = C.Engine(0)
+    if args.serving_only:
+        # the config-5 window: Poisson arrivals at 5 requests/s; the statistics
+        # cover the arrivals after the warm-up
+        launch = tuned_engine_launch(eng, {"mixed": W.c4_jobs(),
+                                           "fp64": W.c4_jobs(count_scale=0.25)}, args.default_launch)
+        log("launch shapes:", launch)
+        out = {}
+        for prec in args.serve_precisions.split(","):
+            out[prec] = serve(eng, args.serve_warmup + args.serve_seconds, 5.0, prec,
+                              warmup_s=args.serve_warmup, progress_s=30.0)
+            log(f"serving {prec}:", out[prec])
+        print(json.dumps({"serving_config5": out}), flush=True)
+        eng.close()
+        return
     jobs = W.c4_jobs()
     # The FP64 launch shape is tuned on a quarter-size sample of the batched
     # workload: each of the tuner's ~15 shapes takes two passes, and a full
@@ -540,6 +572,11 @@ def main():
 
     cpu = None if args.no_cpu else cpu_baseline()
     if cpu:
+        # spectra/hour at the batched workload's mean steps per spectrum
+        per_spectrum = steps_total / args.steps / len(jobs)
+        cpu["spectra_per_hour"] = round(cpu["value"] / per_spectrum * 3600.0, 2)
+        cpu["single_core"]["spectra_per_hour"] = round(
+            cpu["single_core"]["value"] / per_spectrum * 3600.0, 3)
         log("cpu baseline:", cpu)
 
     line = {
