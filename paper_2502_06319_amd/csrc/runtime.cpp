@@ -2078,6 +2078,16 @@ uint64_t pool_particles(cosmica_ctx* ctx)
     return std::min<uint64_t>(want, room / 20);
 }
 
+// Initial entries of a group's work-queue ring: COSMICA_SERVE_RING (a power of
+// two, 64 to 2^26), default 2^20 (16 MB); it doubles as admission needs.
+uint64_t ring_initial()
+{
+    const char* e = std::getenv("COSMICA_SERVE_RING");
+    long long v = e ? std::strtoll(e, nullptr, 10) : 0;
+    if (v < 64 || v > (1ll << 26) || (v & (v - 1)) != 0) return 1ull << 20;
+    return (uint64_t)v;
+}
+
 cosmica_status serve_host_init(cosmica_ctx* ctx)
 {
     auto H = std::make_unique<ServeHost>();
@@ -2213,7 +2223,7 @@ cosmica_status group_create(cosmica_ctx* ctx, int model, int prec, ServeGroup** 
     if ((st = g->mem.alloc(&g->exP, g->pool_cap)) != COSMICA_OK) return st;
     if ((st = g->mem.alloc(&g->exT, g->pool_cap)) != COSMICA_OK) return st;
     if ((st = g->mem.alloc(&g->exNF, g->pool_cap)) != COSMICA_OK) return st;
-    g->ring_cap = 1u << 20;
+    g->ring_cap = ring_initial();
     if ((st = dalloc(ctx, g->ring_cap * sizeof(ChunkDev), (void**)&g->ring_d)) != COSMICA_OK)
         return st;
     g->free_ranges[0] = g->pool_cap;

@@ -168,6 +168,40 @@ def test_parked_particles_survive_a_smaller_kernel_variant(W, short_slices, prec
                 np.testing.assert_array_equal(got[k], alone[k], err_msg=k)
 
 
+def test_work_queue_ring_wraps_and_grows(W, short_slices):
+    """The device work queue is a ring: a small one (1,024 entries, set by
+    COSMICA_SERVE_RING) wraps as staggered requests of 640 chunks each are
+    appended while earlier ones run, and doubles, moving its queued entries to
+    the same positions of the larger ring, when one no longer fits.  Every
+    request still equals its stand-alone result bit for bit."""
+    old = os.environ.get("COSMICA_SERVE_RING")
+    os.environ["COSMICA_SERVE_RING"] = "1024"
+    try:
+        jobs = []
+        for k in range(8):
+            j = W.c2_job(particles_per_bin=1000, n_bins=20, seed=100 + k)
+            j["helio"]["polarity"] = -1 if k % 2 else 1
+            j["job_tag"] = k
+            jobs.append(j)
+        with C.Engine(0) as e:
+            tickets = []
+            for j in jobs:
+                tickets.append(e.submit(j, "mixed"))
+                time.sleep(0.003)
+            for t in tickets:
+                assert t.wait(120000) == C.OK
+            for j, t in zip(jobs, tickets):
+                alone = e.run(j, "mixed")[0]
+                got = t.result()
+                for k in KEYS:
+                    np.testing.assert_array_equal(got[k], alone[k], err_msg=k)
+    finally:
+        if old is None:
+            del os.environ["COSMICA_SERVE_RING"]
+        else:
+            os.environ["COSMICA_SERVE_RING"] = old
+
+
 def test_request_state_and_shedding_a_waiting_request(W, short_slices):
     """cosmica_request_state: 0 while a request waits for admission (here: no
     room in a 30,000-record pool while a 25,000-particle request is resident),
