@@ -366,7 +366,21 @@ cosmica_status cosmica_get_timings(cosmica_ctx* ctx, cosmica_timings* out);
  * resident particle state + exit records stays within the budget, and runs the
  * persistent kernel in bounded slices so that newly admitted jobs join the
  * particles already in flight.  The result buffers must stay valid until the
- * ticket is done.  *ticket receives a positive id. */
+ * ticket is done.  *ticket receives a positive id.
+ *
+ * The worker enqueues each slice before it reads what the previous one did, so
+ * a job is seen to be finished one slice after its last particle exits and is
+ * handed over after the next one (a slice lasts COSMICA_SLICE_MS).  Results
+ * are the same, bit for bit, as cosmica_run of the job alone.  Environment,
+ * read at every slice:
+ *   COSMICA_SLICE_MS     slice length on the device clock, default 6 (ms);
+ *   COSMICA_SLICE_STEPS  if set, a slice also ends after that many steps of
+ *                        each wave (tests use it to force many slices);
+ * and when a context first serves a (model, precision):
+ *   COSMICA_SERVE_POOL   exit records of the admission pool, in particles
+ *                        (default 2^28, at most a 20th of the budget not in use);
+ *   COSMICA_SERVE_RING   initial entries of the device work queue, a power of
+ *                        two from 64 to 2^26 (default 2^20); it grows as needed. */
 cosmica_status cosmica_submit(cosmica_ctx* ctx, const cosmica_job* job,
                               cosmica_precision precision, cosmica_result* result,
                               uint64_t* ticket);
