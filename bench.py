@@ -229,7 +229,7 @@ def serve(eng, seconds, rate, precision, seed=42, cut_at=None, poll_s=0.002, war
         out["cancelled_unadmitted"] = cancelled
         w0, w1 = 0.25 * cut_at, cut_at
         window = [n for t, n in completions if w0 <= t < w1]
-        out["steady_window_s"] = [round(w0, 1), round(w1, 1)]
+        out["steady_window_s"] = [round(w0, 3), round(w1, 3)]
         out["steady_requests"] = len(window)
         out["steady_steps_per_s"] = float(sum(window) / (w1 - w0))
     return out
